@@ -1,0 +1,107 @@
+"""Invariants of the model that pin the oracle (CPU only): fixed points,
+conservation of phi, the momentum balance, and lattice symmetry."""
+import numpy as np
+import pytest
+
+import oracle.orc as orc
+from paper_1507_07294_amd import workloads as wl
+
+
+def test_uniform_state_is_a_fixed_point():
+    """A uniform phi and u with no body force is stationary: mu is uniform,
+    every difference of Eqs. 35-36 vanishes and d_t(phi u) = 0 from the start."""
+    shape = (6, 5, 4)
+    p = wl.ModelParams(sigma=0.01, width=4.0, mobility=0.1, nu=0.05, lambda_g=tuple(np.linspace(0.9, 1.5, 15)))
+    phi0 = np.full((4, 5, 6), 0.3)
+    u0 = np.zeros((3, 4, 5, 6))
+    u0[0], u0[1], u0[2] = 0.01, -0.02, 0.005
+    o = orc.Oracle(shape, (0, 0, 0), orc.COUPLED, p)
+    o.init(phi0, u0)
+    f0, g0, _ = o.get_state()
+    o.step(10)
+    f1, g1, _ = o.get_state()
+    assert np.abs(f1 - f0).max() < 1e-15
+    assert np.abs(g1 - g0).max() < 1e-15
+    assert np.abs(o.read("ux") - 0.01).max() < 1e-15
+    assert np.abs(o.read("p")).max() < 1e-15
+
+
+@pytest.mark.parametrize("bc,coupled", [((0, 0, 0), True), ((0, 0, 1), True), ((1, 1, 1), True),
+                                        ((0, 0, 0), False)])
+def test_phi_is_conserved(bc, coupled):
+    """sum phi is conserved: m_0 of f is invariant, mR_0 = 0, and streaming and
+    bounce-back only permute populations (Eqs. 13, 16, 18)."""
+    shape = (9, 8, 10)
+    w = wl.perturbed_case(shape, bc, 3, coupled=coupled)
+    o = orc.Oracle(shape, bc, orc.COUPLED if coupled else orc.CHE_ONLY, w.params)
+    if not coupled:
+        o.set_velocity(orc.VEL_FIELD, w.u0)
+    o.init(w.phi0, w.u0)
+    t0 = o.totals()[0]
+    scale = np.abs(w.phi0).sum()
+    for _ in range(5):
+        o.step(10)
+        assert abs(o.totals()[0] - t0) < 1e-13 * scale
+
+
+def test_momentum_balance_periodic():
+    """sum_x j(n+1) = sum_x j(n) + sum_x F(n) on a periodic box for any rates:
+    the momentum rows of Eq. 31/32 relax to rho u and add (1 - lambda/2) F,
+    and rho u = j + F/2 by Eq. 29."""
+    shape = (8, 7, 9)
+    w = wl.perturbed_case(shape, (0, 0, 0), 5, coupled=True, gravity=(1e-5, -2e-5, 3e-5))
+    o = orc.Oracle(shape, (0, 0, 0), orc.COUPLED, w.params)
+    o.init(w.phi0, w.u0)
+    for _ in range(8):
+        t = o.totals()
+        o.step(1)
+        t1 = o.totals()
+        assert np.abs(t1[1:4] - (t[1:4] + t[4:7])).max() < 1e-13, (t, t1)
+        assert np.abs(t[4:7]).max() > 1e-6  # the force is really there
+
+
+def test_momentum_conserved_without_force():
+    """With sigma = 0, rho_l = rho_g and no gravity every force vanishes and
+    sum_x j is conserved to round-off."""
+    shape = (8, 7, 9)
+    w = wl.perturbed_case(shape, (0, 0, 0), 6, coupled=True, sigma=0.0, ratio=1.0, gravity=(0, 0, 0))
+    u0 = w.u0 + np.array([0.01, -0.005, 0.002])[:, None, None, None]
+    o = orc.Oracle(shape, (0, 0, 0), orc.COUPLED, w.params)
+    o.init(w.phi0, u0)
+    j0 = o.totals()[1:4]
+    o.step(30)
+    assert np.abs(o.totals()[1:4] - j0).max() < 1e-13
+    assert np.abs(j0).max() > 1e-3
+
+
+def test_xy_swap_symmetry():
+    """Swapping x and y in the initial data swaps the solution: both lattices,
+    the relaxation sets with s_5 = s_6 and lambda_9 = lambda_10, and the
+    stencils are symmetric under the exchange."""
+    shape = (10, 10, 12)
+    w = wl.perturbed_case(shape, (0, 0, 1), 8, coupled=True)
+    p = w.params.replace(s_f=wl.SF_RT, lambda_g=(1.0,) * 15)
+    phi_t = np.swapaxes(w.phi0, 1, 2).copy()
+    u_t = np.swapaxes(w.u0, 2, 3)[[1, 0, 2]].copy()
+    a = orc.Oracle(shape, (0, 0, 1), orc.COUPLED, p)
+    a.init(w.phi0, w.u0)
+    b = orc.Oracle(shape, (0, 0, 1), orc.COUPLED, p)
+    b.init(phi_t, u_t)
+    a.step(20)
+    b.step(20)
+    for fa, fb in (("phi", "phi"), ("p", "p"), ("mu", "mu"), ("ux", "uy"), ("uy", "ux"), ("uz", "uz")):
+        assert np.abs(np.swapaxes(a.read(fa), 1, 2) - b.read(fb)).max() < 1e-14, fa
+
+
+def test_nonfinite_is_reported_with_step_index():
+    shape = (5, 4, 6)
+    w = wl.perturbed_case(shape, (0, 0, 0), 9)
+    o = orc.Oracle(shape, (0, 0, 0), orc.COUPLED, w.params)
+    o.init(w.phi0, w.u0)
+    o.step(2)
+    f, g, pu = o.get_state()
+    g[3, 2, 1, 1] = np.nan
+    o.set_state(g=g)
+    rc, msg = o.try_step(5)
+    assert rc == orc.E_NONFINITE
+    assert "after step 3" in msg
