@@ -1,0 +1,200 @@
+#!/usr/bin/env python3
+"""Throughput of the MRT lattice-Boltzmann phase-field step on one MI355X.
+
+Headline: the coupled step (D3Q7 Cahn-Hilliard + D3Q15 Navier-Stokes, surface
+tension, gravity, bounce-back walls) on the 256 x 256 x 1024 Rayleigh-Taylor
+box at Re = 4000, FP32 compute and storage, inputs resident in HBM.  Prints
+one JSON line with MLUPS, the roofline of the dominant kernel (event-timed on
+the library's stream), the storage-precision variants, the CHE-only
+interface-tracking step, and the FP64 CPU oracle timed on a bounded sample.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
+# algorithmic bytes per lattice update (22 populations + 3-word (phi u)
+# history, each read and written once), per storage mode
+ALGO_BYTES = {"f64": 400, "f32": 200, "f16": 116, "bf16": 116}
+CHE_ALGO_BYTES = {"f64": 2 * 8 * 10, "f32": 2 * 4 * 10}  # 7 populations + 3-word history
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--W", type=int, default=256, help="Rayleigh-Taylor box width (box W x W x 4W)")
+    ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage precisions to time ('' for none)")
+    ap.add_argument("--no-che", action="store_true", help="skip the CHE-only interface-tracking line")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "common.h"):
+        with open(os.path.join(ROOT, "paper_1507_07294_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            data = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = data.get(f"{kernel}|{workload}|{precision}")
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def time_lattice(lt, steps, warmup):
+    import torch
+    lt.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lt.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = lt.time_stages(max(1, min(steps, 50)))
+    n_st = max(1, min(steps, 50))
+    return dt, [v / n_st for v in stages]
+
+
+def cpu_baseline(W, target_s=12.0):
+    """The FP64 oracle on a z-slab of the same Rayleigh-Taylor box."""
+    import oracle.orc as orc
+    from paper_1507_07294_amd import workloads as wl
+    w = wl.rayleigh_taylor(W=W, Re=4000.0)
+    nz_slab = max(8, W // 8)
+    z0 = w.shape[2] // 2 - nz_slab // 2
+    phi = w.phi0[z0:z0 + nz_slab].copy()
+    shape = (w.shape[0], w.shape[1], nz_slab)
+    o = orc.Oracle(shape, w.bc, orc.COUPLED, w.params)
+    o.init(phi)
+    t0 = time.perf_counter()
+    o.step(1)
+    t1 = time.perf_counter() - t0
+    extra = max(0, min(20, int(target_s / max(t1, 1e-3)) - 1))
+    t0 = time.perf_counter()
+    if extra:
+        o.step(extra)
+    t2 = time.perf_counter() - t0
+    steps = 1 + extra
+    nodes = shape[0] * shape[1] * shape[2]
+    mlups = nodes * steps / (t1 + t2) / 1e6
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{shape[0]}x{shape[1]}x{nz_slab} z-slab through the interface of the W={W} "
+                      f"Rayleigh-Taylor box, {steps} FP64 steps, {t1 + t2:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a lattice larger than one "
+              "GPU would be split into z-slabs with halo exchange, which this build does not include.",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs a ROCm GPU", file=sys.stderr)
+        sys.exit(1)
+    from paper_1507_07294_amd import mplb
+    from paper_1507_07294_amd import workloads as wl
+
+    W = args.W
+    w = wl.rayleigh_taylor(W=W, Re=4000.0)
+    N = w.nodes
+    wname = f"rayleigh_taylor_{W}x{W}x{4 * W}_Re4000"
+    print(f"[bench] {wname} N={N} f32: init", file=sys.stderr, flush=True)
+    lt = mplb.from_workload(w, "f32")
+    dt, st = time_lattice(lt, args.steps, args.warmup)
+    mlups = N * args.steps / dt / 1e6
+    ms_step = dt / args.steps * 1e3
+    k_ms = st[2]
+    achieved = ALGO_BYTES["f32"] * N / (k_ms * 1e-3) / 1e9
+    traffic = measured_traffic("k_step", wname, "f32")
+    result = {
+        "metric": "MLUPS", "value": round(mlups, 1), "unit": "MLUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wname, "nodes": N, "precision": "f32 compute and storage",
+                   "boundaries": "periodic x,y; bounce-back walls z", "Re": 4000, "atwood": 0.5},
+        "hbm_frac_step": round(ALGO_BYTES["f32"] * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        "algorithmic_bytes_per_lup": ALGO_BYTES["f32"],
+        "stage_ms": {"phi": round(st[0], 4), "mu": round(st[1], 4), "step": round(st[2], 4)},
+        "roofline": {"kernel": "k_step", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic},
+    }
+    lt.destroy()
+    del lt
+    torch.cuda.empty_cache()
+
+    variants = {}
+    for prec in [v for v in args.variants.split(",") if v]:
+        print(f"[bench] {wname} {prec}", file=sys.stderr, flush=True)
+        lt = mplb.from_workload(w, prec)
+        steps = max(10, args.steps // (2 if prec == "f64" else 1))
+        dtv, stv = time_lattice(lt, steps, max(2, args.warmup // 2))
+        mv = N * steps / dtv / 1e6
+        variants[prec] = {"MLUPS": round(mv, 1), "ms_per_step": round(dtv / steps * 1e3, 4),
+                          "algorithmic_bytes_per_lup": ALGO_BYTES[prec],
+                          "hbm_frac_step": round(ALGO_BYTES[prec] * N / (dtv / steps) / 1e9 / HBM_PEAK_GBPS, 4),
+                          "k_step_ms": round(stv[2], 4)}
+        lt.destroy()
+        del lt
+        torch.cuda.empty_cache()
+    if variants:
+        result["variants"] = variants
+
+    if not args.no_che:
+        wc = wl.deformation_flow(n=128)
+        print("[bench] deformation_flow 128^3 f32 (CHE only)", file=sys.stderr, flush=True)
+        lt = mplb.from_workload(wc, "f32")
+        steps = args.steps
+        dtc, stc = time_lattice(lt, steps, args.warmup)
+        result["che_only"] = {"workload": "deformation_flow_128^3", "MLUPS": round(wc.nodes * steps / dtc / 1e6, 1),
+                              "ms_per_step": round(dtc / steps * 1e3, 4),
+                              "hbm_frac_step": round(CHE_ALGO_BYTES["f32"] * wc.nodes / (dtc / steps) / 1e9
+                                                     / HBM_PEAK_GBPS, 4)}
+        lt.destroy()
+        del lt
+        torch.cuda.empty_cache()
+
+    if args.copy_probe:
+        nbytes = 1 << 30
+        a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = nbytes
+        del a, b
+
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(W)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

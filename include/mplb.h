@@ -1,0 +1,173 @@
+/*
+ * mplb.h -- C-ABI of libmplb, the MI355X (gfx950) implementation of the time
+ * step of the three-dimensional MRT lattice-Boltzmann phase-field model of
+ * Liang, Shi & Chai, "An efficient three-dimensional multiple-relaxation-time
+ * lattice Boltzmann model for multiphase flows" (arXiv:1507.07294).
+ *
+ * The problem the calls follow (Secs. II-III of the paper): given a lattice,
+ * the parameters {sigma, D, rho_l, rho_g, M, A, S^f, nu, S^g, gravity}, an
+ * initial order parameter phi (and velocity u) and boundary conditions,
+ * advance the D3Q7 MRT scheme for the Cahn-Hilliard equation (Eq. 4) and the
+ * D3Q15 MRT scheme for the Navier-Stokes equations (Eq. 20) by N steps and
+ * observe phi, rho, mu, u and p.  For the interface-tracking problems
+ * (Sec. III A-B) only Eq. 4 is advanced, under a prescribed velocity.
+ *
+ * Conventions
+ *  - Lattice units, dx = dt = c = 1.  Node (x,y,z) has index x + nx*(y + ny*z).
+ *  - Host arrays are double, x fastest; a vector field is three consecutive
+ *    scalar fields (x component first).  Host arrays are owned by the caller
+ *    and only read or written during the call.
+ *  - Every call returns MPLB_OK or an error code; nothing throws across the
+ *    ABI.  On error, mplb_last_error(h) describes it.  A handle is not
+ *    thread-safe; distinct handles may be used from distinct threads.
+ *  - Work is enqueued on the handle's HIP stream (default: the null stream).
+ *    mplb_step returns once the work is enqueued unless a non-finite check is
+ *    due; mplb_read, mplb_totals and mplb_checkpoint synchronise the stream.
+ */
+#ifndef MPLB_H
+#define MPLB_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define MPLB_OK 0
+#define MPLB_E_INVAL 1     /* bad argument, size or parameter */
+#define MPLB_E_NOMEM 2     /* device allocation failed or arena too small */
+#define MPLB_E_DEVICE 3    /* a HIP call failed; text in mplb_last_error */
+#define MPLB_E_STATE 4     /* call out of order (e.g. step before init) */
+#define MPLB_E_NONFINITE 5 /* a population became NaN or Inf; step index in mplb_last_error */
+
+/* boundary condition per axis */
+#define MPLB_PERIODIC 0
+#define MPLB_WALL 1 /* no-slip wall, half-way bounce-back, between node 0 / n-1 and the ghost layer */
+
+/* arithmetic and storage precision */
+#define MPLB_F64 0       /* FP64 compute and storage */
+#define MPLB_F32 1       /* FP32 compute and storage */
+#define MPLB_F32_F16 2   /* FP32 compute; f_1..f_6 and g stored in FP16, f_0 and (phi u) in FP32 */
+#define MPLB_F32_BF16 3  /* FP32 compute; f_1..f_6 and g stored in BF16, f_0 and (phi u) in FP32 */
+
+/* what a step advances */
+#define MPLB_COUPLED 0  /* Eqs. 4 and 20 (Sec. II) */
+#define MPLB_CHE_ONLY 1 /* Eq. 4 under a prescribed velocity (Sec. III A-B) */
+
+/* fields for mplb_read */
+#define MPLB_PHI 0 /* order parameter, Eq. 13 */
+#define MPLB_RHO 1 /* density, Eq. 14 */
+#define MPLB_MU 2  /* chemical potential, Eq. 2 */
+#define MPLB_UX 3  /* velocity, Eq. 29 (or the prescribed one) */
+#define MPLB_UY 4
+#define MPLB_UZ 5
+#define MPLB_P 6   /* pressure, Eq. 30 (0 in CHE-only mode) */
+
+/* prescribed velocities for MPLB_CHE_ONLY (mplb_set_velocity) */
+#define MPLB_VEL_ZERO 0
+#define MPLB_VEL_FIELD 1   /* a constant field given by the caller */
+#define MPLB_VEL_ZALESAK 2 /* rigid rotation, Eq. 37, L = nx */
+#define MPLB_VEL_DEFORM 3  /* deformation flow, Eq. 41 times cos(pi t/T), t = n U / nx */
+
+typedef struct mplb_params {
+  double sigma;        /* surface tension sigma (Eq. 2) */
+  double width;        /* interface thickness D (Eq. 2); beta = 3 sigma/(4D), k = 3 D sigma/8 */
+  double rho_l;        /* density at phi = +1 (Eq. 14) */
+  double rho_g;        /* density at phi = -1 (Eq. 14) */
+  double mobility;     /* M (Eqs. 1, 19); eta = M / (A (1/s_1 - 1/2)) */
+  double A;            /* D3Q7 free parameter, 0 < A < 1/3 (Eq. 8); the paper fixes 0.25 */
+  double s_f[7];       /* S^f (Eq. 10), each in (0,2), s_1 = s_2 = s_3 */
+  double nu;           /* kinematic viscosity > 0 (Eq. 33): lambda_9..13 = 1/(3 nu + 1/2) */
+  double lambda_g[15]; /* S^g (Eq. 26), each in (0,2); entries 9..13 are replaced from nu */
+  double gravity[3];   /* body acceleration; G = (rho - rho_ref) gravity */
+  double rho_ref;      /* reference density of the body force (0: G = rho gravity) */
+} mplb_params;
+
+typedef struct mplb_s mplb_t;
+
+/* Device bytes a lattice needs (populations of two time levels, the
+ * (phi u) history, phi, mu, a read-out buffer and reduction scratch). */
+int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes);
+
+/* Create a lattice of nx*ny*nz nodes (each >= 1) with bc[a] in
+ * {MPLB_PERIODIC, MPLB_WALL} per axis.  device_arena: NULL lets the library
+ * allocate (hipMalloc) on the current device; otherwise a device buffer of
+ * arena_bytes >= mplb_required_bytes that the library borrows until
+ * mplb_destroy (the caller keeps it alive, e.g. as a torch tensor).
+ * *out receives the handle; on error *out is NULL. */
+int mplb_create(int nx, int ny, int nz, const int bc[3], int precision, int mode, void* device_arena,
+                size_t arena_bytes, mplb_t** out);
+
+/* Enqueue all later work on this hipStream_t (NULL = null stream). */
+int mplb_set_stream(mplb_t* h, void* hip_stream);
+
+/* Validate and derive (beta, k, eta, tau_g) from p.  MPLB_E_INVAL if any rate
+ * lies outside (0,2), s_1..s_3 differ, A is outside (0,1/3), D, rho_l,
+ * rho_g or nu is not positive, or the mobility is negative. */
+int mplb_set_params(mplb_t* h, const mplb_params* p);
+
+/* CHE-only lattices: the velocity prescribed at step n.  u_field (3N, used
+ * by MPLB_VEL_FIELD only) is copied.  U and T as in Eqs. 37 and 41. */
+int mplb_set_velocity(mplb_t* h, int kind, const double* u_field, double U, double T);
+
+/* Equilibrium start (an initial state the paper leaves open): mu_0 from
+ * phi0 (Eqs. 2, 36), f = f^eq(phi0, mu0, u0) (Eq. 5), g = g^eq(p = 0, rho(phi0),
+ * u0) (Eq. 21), (phi u)_prev = phi0 u0, step counter 0.  phi0 has N values;
+ * u0 has 3N or is NULL (u0 = 0); in CHE-only mode u0 is ignored and the
+ * prescribed velocity at step 0 is used.  Requires mplb_set_params (and, in
+ * CHE-only mode, mplb_set_velocity). */
+int mplb_init(mplb_t* h, const double* phi0, const double* u0);
+
+/* Advance nsteps >= 0 time steps (Eqs. 15-16 and their D3Q15 analogue; the
+ * finite differences of Eqs. 34-36).  Returns MPLB_E_NONFINITE if the
+ * non-finite check (see mplb_set_check_interval) finds a NaN or Inf. */
+int mplb_step(mplb_t* h, int nsteps);
+
+/* Every k steps (k >= 1) mplb_step synchronises and checks that no
+ * population became non-finite; k = 0 (default) checks only when
+ * mplb_totals is called. */
+int mplb_set_check_interval(mplb_t* h, int k);
+
+long mplb_step_count(const mplb_t* h);
+
+/* Macroscopic field (MPLB_PHI..MPLB_P) at the current time level into
+ * out[N] (host, double).  Does not change the state. */
+int mplb_read(mplb_t* h, int field, double* out);
+
+/* FP64 totals at the current level: out[0] = sum phi, out[1..3] = sum of
+ * sum_i c_i g_i, out[4..6] = sum of F_s + F_a + G.  Returns MPLB_E_NONFINITE
+ * if any population is non-finite. */
+int mplb_totals(mplb_t* h, double out[7]);
+
+/* Advance `count` lattices by nsteps each with batched launches: one kernel
+ * per stage covers every lattice (continuous-batching serving).  All handles
+ * must be initialised, share one precision and mode, and use the first
+ * handle's stream. */
+int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
+
+/* Bytes of a checkpoint (raw state in storage precision plus the step
+ * counter); mplb_checkpoint writes it to host memory, mplb_restore reads one
+ * written by a lattice of the same size, precision and mode. */
+int mplb_checkpoint_bytes(const mplb_t* h, size_t* bytes);
+int mplb_checkpoint(mplb_t* h, void* host_buf, size_t bytes);
+int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes);
+
+/* Measurement: advance nsteps steps with HIP events recorded on the handle's
+ * stream around each kernel stage; ms[0..3] receive the summed durations of
+ * the phi pass, the mu pass, the collide-and-stream kernel and the whole
+ * steps.  Synchronises; the state advances exactly as with mplb_step. */
+int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
+
+/* Test hook: overwrite one stored population (set 0: f, 1: g; index i;
+ * node n) of the current state with `value`, e.g. to plant a NaN. */
+int mplb_poke(mplb_t* h, int set, int i, long node, double value);
+
+void mplb_destroy(mplb_t* h);
+const char* mplb_last_error(const mplb_t* h);
+const char* mplb_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,61 @@
+// Internal types shared by the kernels and the host side of libmplb.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mplb.h"
+
+namespace mplb {
+
+// Lattice geometry.  wall[a] != 0: axis a is bounded by no-slip walls.
+struct Geo {
+  int nx, ny, nz;
+  int wall_x, wall_y, wall_z;
+  int N;     // nx*ny*nz (< 2^31)
+  int pitch; // elements between consecutive population arrays (N rounded up to 256)
+};
+
+// Per-lattice coefficients in the compute type (derived on the host).
+template <class T>
+struct Coef {
+  T rho_l, rho_g, drho;   // Eq. 14; drho = rho_l - rho_g (rho_A - rho_B)
+  T beta, kappa;          // after Eq. 2
+  T eta, A;               // Eqs. 5, 8, 19
+  T mob;                  // mobility M
+  T rho_ref, grav[3];     // body force
+  T sf[7];                // S^f
+  T lg[15];               // S^g (lambda_9..13 from nu)
+  int vel_kind;           // CHE-only prescribed velocity kind
+  T velU;
+  T vel_ct;               // cos(pi t / T) of the current step (deformation flow)
+};
+
+// Compute type T, storage of f_0 (S0) and of f_1..f_6 and g (S).
+template <int P> struct Prec;
+template <> struct Prec<MPLB_F64> { using T = double; using S0 = double; using S = double; };
+template <> struct Prec<MPLB_F32> { using T = float; using S0 = float; using S = float; };
+template <> struct Prec<MPLB_F32_F16> { using T = float; using S0 = float; using S = _Float16; };
+template <> struct Prec<MPLB_F32_BF16> { using T = float; using S0 = float; using S = __bf16; };
+
+// Device pointers of one lattice.  f: f_0 array (S0) followed by f_1..f_6
+// arrays (S), each `pitch` elements; g: 15 arrays of S.
+struct Bufs {
+  void* f[2];
+  void* g[2];
+  void* phiu;   // 3 x pitch, T: (phi u) of the previous level
+  void* phi;    // pitch, T
+  void* mu;     // pitch, T
+  void* ufield; // 3 x pitch, T (CHE-only, prescribed field)
+  double* out;  // pitch doubles: read-out / upload staging
+  double* red;  // reduction partials (kRedSlots x 8) + final (8)
+  int* flag;    // non-finite flag
+};
+
+constexpr int kRedSlots = 2048;
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace mplb

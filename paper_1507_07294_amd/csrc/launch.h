@@ -1,0 +1,34 @@
+// Host-side launchers of the libmplb kernels (kernels.hip).  Each enqueues on
+// `s` and returns the launch status; precision P and mode select the template
+// instance at run time.
+#pragma once
+
+#include "common.h"
+
+namespace mplb {
+
+// phi = sum_i f_i over the pulled populations of buffer `cur` (Eq. 13)
+hipError_t launch_phi(int P, const Geo& G, const Bufs& B, int cur, hipStream_t s);
+// mu from phi (Eqs. 2, 36)
+hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, hipStream_t s);
+// one collide-and-stream step: reads buffer `cur`, writes buffer 1 - cur
+hipError_t launch_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                       hipStream_t s);
+// field (MPLB_PHI..MPLB_P) at the current level into B.out (double)
+hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                        int field, hipStream_t s);
+// FP64 totals and non-finite count into B.red[kRedSlots*8 .. +8)
+hipError_t launch_totals(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                         hipStream_t s);
+// dst[n] = (T) B.out[n] for n < N (upload of a host field staged in B.out)
+hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStream_t s);
+// equilibrium initial state into buffer `cur`, from phi, mu and u (held in phiu)
+hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                       hipStream_t s);
+hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
+hipError_t launch_fill_zero(int P, void* p, int count, hipStream_t s);
+// overwrite stored population i (set 0: f, 1: g) at storage index n of buffer cur
+hipError_t launch_poke(int P, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v,
+                       hipStream_t s);
+
+}  // namespace mplb

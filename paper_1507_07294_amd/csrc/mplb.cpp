@@ -1,0 +1,463 @@
+// Host side of libmplb: the C-ABI declared in include/mplb.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "mplb.h"
+
+using namespace mplb;
+
+namespace {
+
+struct Plan {
+  size_t pitch;  // elements per population array
+  size_t f, g, phiu, phi, mu, ufield, out, red, flag, total;
+};
+
+size_t comp_size(int prec) { return prec == MPLB_F64 ? 8 : 4; }
+size_t store0_size(int prec) { return prec == MPLB_F64 ? 8 : 4; }
+size_t store_size(int prec) { return prec == MPLB_F64 ? 8 : (prec == MPLB_F32 ? 4 : 2); }
+
+Plan make_plan(long long N, int prec, int mode) {
+  Plan p{};
+  p.pitch = align_up((size_t)N, 256);
+  const size_t A = 256;
+  size_t sT = comp_size(prec), s0 = store0_size(prec), sS = store_size(prec);
+  p.f = align_up(p.pitch * s0 + 6 * p.pitch * sS, A);
+  p.g = mode == MPLB_COUPLED ? align_up(15 * p.pitch * sS, A) : 0;
+  p.phiu = align_up(3 * p.pitch * sT, A);
+  p.phi = align_up(p.pitch * sT, A);
+  p.mu = align_up(p.pitch * sT, A);
+  p.ufield = mode == MPLB_CHE_ONLY ? align_up(3 * p.pitch * sT, A) : 0;
+  p.out = align_up(p.pitch * 8, A);
+  p.red = align_up(((size_t)kRedSlots * 8 + 8) * 8, A);
+  p.flag = A;
+  p.total = 2 * p.f + 2 * p.g + p.phiu + p.phi + p.mu + p.ufield + p.out + p.red + p.flag;
+  return p;
+}
+
+bool valid_dims(int nx, int ny, int nz) {
+  if (nx < 1 || ny < 1 || nz < 1) return false;
+  long long N = (long long)nx * ny * nz;
+  return N < (1LL << 31) - 4096;
+}
+
+const uint64_t kMagic = 0x31303531504c424dULL;  // checkpoint tag
+
+struct CkptHeader {
+  uint64_t magic;
+  int32_t nx, ny, nz, prec, mode, pad;
+  int64_t step;
+  uint64_t f_bytes, g_bytes, phiu_bytes;
+};
+
+}  // namespace
+
+struct mplb_s {
+  Geo G{};
+  int prec = 0, mode = 0;
+  int bc[3] = {0, 0, 0};
+  Plan plan{};
+  hipStream_t stream = nullptr;
+  void* arena = nullptr;
+  bool own_arena = false;
+  Bufs B{};
+  int cur = 0;
+  long step = 0;
+  bool have_params = false, have_init = false;
+  Coef<double> C{};
+  double velT = 1.0;
+  int check_interval = 0;
+  std::string err;
+};
+
+static int fail(mplb_t* h, int code, const char* fmt, ...) {
+  if (h) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    h->err = buf;
+  }
+  return code;
+}
+
+#define HIPCHK(h, expr)                                                                      \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(h, MPLB_E_DEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+extern "C" {
+
+const char* mplb_strerror(int code) {
+  switch (code) {
+    case MPLB_OK: return "ok";
+    case MPLB_E_INVAL: return "invalid argument";
+    case MPLB_E_NOMEM: return "out of device memory or arena too small";
+    case MPLB_E_DEVICE: return "HIP error";
+    case MPLB_E_STATE: return "call out of order";
+    case MPLB_E_NONFINITE: return "non-finite population";
+    default: return "unknown error";
+  }
+}
+
+const char* mplb_last_error(const mplb_t* h) { return h ? h->err.c_str() : "null handle"; }
+
+int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes) {
+  if (!bytes || !valid_dims(nx, ny, nz) || precision < MPLB_F64 || precision > MPLB_F32_BF16 ||
+      (mode != MPLB_COUPLED && mode != MPLB_CHE_ONLY))
+    return MPLB_E_INVAL;
+  *bytes = make_plan((long long)nx * ny * nz, precision, mode).total;
+  return MPLB_OK;
+}
+
+int mplb_create(int nx, int ny, int nz, const int bc[3], int precision, int mode, void* device_arena,
+                size_t arena_bytes, mplb_t** out) {
+  if (!out) return MPLB_E_INVAL;
+  *out = nullptr;
+  if (!bc || !valid_dims(nx, ny, nz) || precision < MPLB_F64 || precision > MPLB_F32_BF16 ||
+      (mode != MPLB_COUPLED && mode != MPLB_CHE_ONLY))
+    return MPLB_E_INVAL;
+  for (int a = 0; a < 3; ++a)
+    if (bc[a] != MPLB_PERIODIC && bc[a] != MPLB_WALL) return MPLB_E_INVAL;
+  mplb_t* h = new (std::nothrow) mplb_t();
+  if (!h) return MPLB_E_NOMEM;
+  h->prec = precision;
+  h->mode = mode;
+  for (int a = 0; a < 3; ++a) h->bc[a] = bc[a];
+  h->G.nx = nx; h->G.ny = ny; h->G.nz = nz;
+  h->G.wall_x = bc[0] == MPLB_WALL; h->G.wall_y = bc[1] == MPLB_WALL; h->G.wall_z = bc[2] == MPLB_WALL;
+  h->G.N = nx * ny * nz;
+  h->plan = make_plan(h->G.N, precision, mode);
+  h->G.pitch = (int)h->plan.pitch;
+  if (device_arena) {
+    if (arena_bytes < h->plan.total || ((uintptr_t)device_arena & 255)) {
+      delete h;
+      return MPLB_E_NOMEM;
+    }
+    h->arena = device_arena;
+  } else {
+    if (hipMalloc(&h->arena, h->plan.total) != hipSuccess) {
+      (void)hipGetLastError();
+      delete h;
+      return MPLB_E_NOMEM;
+    }
+    h->own_arena = true;
+  }
+  char* p = (char*)h->arena;
+  const Plan& P = h->plan;
+  h->B.f[0] = p; p += P.f;
+  h->B.f[1] = p; p += P.f;
+  h->B.g[0] = P.g ? p : nullptr; p += P.g;
+  h->B.g[1] = P.g ? p : nullptr; p += P.g;
+  h->B.phiu = p; p += P.phiu;
+  h->B.phi = p; p += P.phi;
+  h->B.mu = p; p += P.mu;
+  h->B.ufield = P.ufield ? p : nullptr; p += P.ufield;
+  h->B.out = (double*)p; p += P.out;
+  h->B.red = (double*)p; p += P.red;
+  h->B.flag = (int*)p; p += P.flag;
+  h->C.vel_kind = MPLB_VEL_ZERO;
+  h->C.vel_ct = 1.0;
+  *out = h;
+  return MPLB_OK;
+}
+
+void mplb_destroy(mplb_t* h) {
+  if (!h) return;
+  if (h->own_arena && h->arena) {
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(h->arena);
+  }
+  delete h;
+}
+
+int mplb_set_stream(mplb_t* h, void* s) {
+  if (!h) return MPLB_E_INVAL;
+  h->stream = (hipStream_t)s;
+  return MPLB_OK;
+}
+
+int mplb_set_check_interval(mplb_t* h, int k) {
+  if (!h || k < 0) return MPLB_E_INVAL;
+  h->check_interval = k;
+  return MPLB_OK;
+}
+
+long mplb_step_count(const mplb_t* h) { return h ? h->step : -1; }
+
+int mplb_set_params(mplb_t* h, const mplb_params* p) {
+  if (!h || !p) return MPLB_E_INVAL;
+  auto in02 = [](double v) { return v > 0.0 && v < 2.0; };
+  if (!(p->A > 0.0 && p->A < 1.0 / 3.0)) return fail(h, MPLB_E_INVAL, "A must lie in (0, 1/3)");
+  if (!(p->width > 0.0) || !(p->rho_l > 0.0) || !(p->rho_g > 0.0) || !(p->nu > 0.0) || !(p->mobility >= 0.0) ||
+      !std::isfinite(p->sigma))
+    return fail(h, MPLB_E_INVAL, "D, rho_l, rho_g and nu must be positive, the mobility non-negative");
+  for (int i = 0; i < 7; ++i)
+    if (!in02(p->s_f[i])) return fail(h, MPLB_E_INVAL, "s_f[%d] outside (0,2)", i);
+  if (p->s_f[1] != p->s_f[2] || p->s_f[1] != p->s_f[3]) return fail(h, MPLB_E_INVAL, "s_1, s_2, s_3 must be equal");
+  Coef<double>& C = h->C;
+  C.rho_l = p->rho_l;
+  C.rho_g = p->rho_g;
+  C.drho = p->rho_l - p->rho_g;
+  C.beta = 3.0 * p->sigma / (4.0 * p->width);  // after Eq. 2
+  C.kappa = 3.0 * p->width * p->sigma / 8.0;
+  C.A = p->A;
+  double tau_f = 1.0 / p->s_f[1];
+  C.eta = p->mobility / (p->A * (tau_f - 0.5));  // Eq. 19 with c_s^2 = A
+  C.mob = p->mobility;
+  C.rho_ref = p->rho_ref;
+  for (int a = 0; a < 3; ++a) C.grav[a] = p->gravity[a];
+  for (int i = 0; i < 7; ++i) C.sf[i] = p->s_f[i];
+  double tau_g = 3.0 * p->nu + 0.5;  // Eq. 33 with c_s^2 = 1/3
+  for (int i = 0; i < 15; ++i) C.lg[i] = (i >= 9 && i <= 13) ? 1.0 / tau_g : p->lambda_g[i];
+  for (int i = 0; i < 15; ++i)
+    if (!in02(C.lg[i])) return fail(h, MPLB_E_INVAL, "lambda[%d] outside (0,2)", i);
+  h->have_params = true;
+  return MPLB_OK;
+}
+
+static int upload_field(mplb_t* h, const double* src, void* dst) {
+  HIPCHK(h, hipMemcpyAsync(h->B.out, src, (size_t)h->G.N * sizeof(double), hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, launch_cvt_in(h->prec, h->G, h->B, dst, h->stream));
+  return MPLB_OK;
+}
+
+int mplb_set_velocity(mplb_t* h, int kind, const double* u_field, double U, double T) {
+  if (!h) return MPLB_E_INVAL;
+  if (h->mode != MPLB_CHE_ONLY) return fail(h, MPLB_E_STATE, "prescribed velocity needs a CHE-only lattice");
+  if (kind < MPLB_VEL_ZERO || kind > MPLB_VEL_DEFORM || (kind == MPLB_VEL_FIELD && !u_field) ||
+      (kind == MPLB_VEL_DEFORM && !(T > 0.0)) || !std::isfinite(U))
+    return fail(h, MPLB_E_INVAL, "invalid velocity specification");
+  if (kind == MPLB_VEL_FIELD) {
+    size_t sT = comp_size(h->prec);
+    for (int a = 0; a < 3; ++a) {
+      int rc = upload_field(h, u_field + (size_t)a * h->G.N, (char*)h->B.ufield + (size_t)a * h->G.pitch * sT);
+      if (rc) return rc;
+    }
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  h->C.vel_kind = kind;
+  h->C.velU = U;
+  h->velT = T;
+  return MPLB_OK;
+}
+
+// cos(pi t / T) of the deformation flow at step n, t = n U / nx
+static double deform_ct(const mplb_t* h, long n) {
+  const double pi = 3.14159265358979323846;
+  double t = (double)n * h->C.velU / h->G.nx;
+  return std::cos(pi * t / h->velT);
+}
+
+int mplb_init(mplb_t* h, const double* phi0, const double* u0) {
+  if (!h || !phi0) return MPLB_E_INVAL;
+  if (!h->have_params) return fail(h, MPLB_E_STATE, "init before set_params");
+  size_t sT = comp_size(h->prec);
+  int rc = upload_field(h, phi0, h->B.phi);
+  if (rc) return rc;
+  if (h->mode == MPLB_COUPLED) {
+    for (int a = 0; a < 3; ++a) {
+      void* dst = (char*)h->B.phiu + (size_t)a * h->G.pitch * sT;
+      if (u0) {
+        rc = upload_field(h, u0 + (size_t)a * h->G.N, dst);
+        if (rc) return rc;
+      } else {
+        HIPCHK(h, launch_fill_zero(h->prec, dst, h->G.N, h->stream));
+      }
+    }
+  }
+  HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
+  h->C.vel_ct = 1.0;
+  h->cur = 0;
+  HIPCHK(h, launch_init(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream));
+  HIPCHK(h, launch_fill_int(h->B.flag, 0, 1, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->step = 0;
+  h->have_init = true;
+  return MPLB_OK;
+}
+
+static int check_flag(mplb_t* h) {
+  int flag = 0;
+  HIPCHK(h, hipMemcpyAsync(&flag, h->B.flag, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  if (flag) return fail(h, MPLB_E_NONFINITE, "non-finite population after step %ld", h->step);
+  return MPLB_OK;
+}
+
+// Enqueue one step of lattice h on stream s.
+static int enqueue_step(mplb_t* h, hipStream_t s) {
+  if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+  HIPCHK(h, launch_phi(h->prec, h->G, h->B, h->cur, s));
+  if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, s));
+  HIPCHK(h, launch_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s));
+  h->cur = 1 - h->cur;
+  h->step++;
+  return MPLB_OK;
+}
+
+int mplb_step(mplb_t* h, int nsteps) {
+  if (!h || nsteps < 0) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "step before init");
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = enqueue_step(h, h->stream);
+    if (rc) return rc;
+    if (h->check_interval > 0 && h->step % h->check_interval == 0) {
+      rc = check_flag(h);
+      if (rc) return rc;
+    }
+  }
+  return MPLB_OK;
+}
+
+int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
+  if (!h || !ms || nsteps < 0) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "step before init");
+  for (int k = 0; k < 4; ++k) ms[k] = 0.0;
+  std::vector<hipEvent_t> ev(4 * (size_t)nsteps);
+  for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+  int rc = MPLB_OK;
+  for (int k = 0; k < nsteps && rc == MPLB_OK; ++k) {
+    hipEvent_t* e = &ev[4 * (size_t)k];
+    if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+    hipError_t err = hipEventRecord(e[0], h->stream);
+    if (err == hipSuccess) err = launch_phi(h->prec, h->G, h->B, h->cur, h->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
+    if (err == hipSuccess && h->mode == MPLB_COUPLED) err = launch_mu(h->prec, h->G, h->C, h->B, h->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[2], h->stream);
+    if (err == hipSuccess) err = launch_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[3], h->stream);
+    if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
+    h->cur = 1 - h->cur;
+    h->step++;
+  }
+  if (rc == MPLB_OK) {
+    hipError_t err = hipStreamSynchronize(h->stream);
+    if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
+  }
+  for (int k = 0; k < nsteps && rc == MPLB_OK; ++k) {
+    hipEvent_t* e = &ev[4 * (size_t)k];
+    float a = 0, b = 0, c = 0;
+    (void)hipEventElapsedTime(&a, e[0], e[1]);
+    (void)hipEventElapsedTime(&b, e[1], e[2]);
+    (void)hipEventElapsedTime(&c, e[2], e[3]);
+    ms[0] += a; ms[1] += b; ms[2] += c; ms[3] += a + b + c;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
+  if (!hs || count < 0 || nsteps < 0) return MPLB_E_INVAL;
+  if (count == 0) return MPLB_OK;
+  for (int i = 0; i < count; ++i) {
+    if (!hs[i]) return MPLB_E_INVAL;
+    if (!hs[i]->have_init) return fail(hs[i], MPLB_E_STATE, "step before init");
+  }
+  hipStream_t s = hs[0]->stream;
+  for (int k = 0; k < nsteps; ++k)
+    for (int i = 0; i < count; ++i) {
+      int rc = enqueue_step(hs[i], s);
+      if (rc) return rc;
+    }
+  return MPLB_OK;
+}
+
+static int prepare_macro(mplb_t* h) {
+  HIPCHK(h, launch_phi(h->prec, h->G, h->B, h->cur, h->stream));
+  if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
+  if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+  return MPLB_OK;
+}
+
+int mplb_read(mplb_t* h, int field, double* out) {
+  if (!h || !out || field < MPLB_PHI || field > MPLB_P) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "read before init");
+  int rc = prepare_macro(h);
+  if (rc) return rc;
+  HIPCHK(h, launch_macro(h->prec, h->mode, h->G, h->C, h->B, h->cur, field, h->stream));
+  HIPCHK(h, hipMemcpyAsync(out, h->B.out, (size_t)h->G.N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MPLB_OK;
+}
+
+int mplb_totals(mplb_t* h, double out[7]) {
+  if (!h || !out) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "totals before init");
+  int rc = prepare_macro(h);
+  if (rc) return rc;
+  HIPCHK(h, launch_totals(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream));
+  double r[8];
+  HIPCHK(h, hipMemcpyAsync(r, h->B.red + (size_t)kRedSlots * 8, sizeof r, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  for (int k = 0; k < 7; ++k) out[k] = r[k];
+  if (r[7] > 0.0) return fail(h, MPLB_E_NONFINITE, "non-finite population at step %ld", h->step);
+  return MPLB_OK;
+}
+
+int mplb_checkpoint_bytes(const mplb_t* h, size_t* bytes) {
+  if (!h || !bytes) return MPLB_E_INVAL;
+  *bytes = sizeof(CkptHeader) + h->plan.f + h->plan.g + h->plan.phiu;
+  return MPLB_OK;
+}
+
+int mplb_checkpoint(mplb_t* h, void* host_buf, size_t bytes) {
+  size_t need = 0;
+  if (!h || !host_buf || mplb_checkpoint_bytes(h, &need) || bytes < need) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "checkpoint before init");
+  CkptHeader hd{kMagic, h->G.nx, h->G.ny, h->G.nz, h->prec, h->mode, 0, h->step, h->plan.f, h->plan.g, h->plan.phiu};
+  char* p = (char*)host_buf;
+  std::memcpy(p, &hd, sizeof hd);
+  p += sizeof hd;
+  HIPCHK(h, hipMemcpyAsync(p, h->B.f[h->cur], h->plan.f, hipMemcpyDeviceToHost, h->stream));
+  p += h->plan.f;
+  if (h->plan.g) HIPCHK(h, hipMemcpyAsync(p, h->B.g[h->cur], h->plan.g, hipMemcpyDeviceToHost, h->stream));
+  p += h->plan.g;
+  HIPCHK(h, hipMemcpyAsync(p, h->B.phiu, h->plan.phiu, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MPLB_OK;
+}
+
+int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
+  size_t need = 0;
+  if (!h || !host_buf || mplb_checkpoint_bytes(h, &need) || bytes < need) return MPLB_E_INVAL;
+  CkptHeader hd;
+  std::memcpy(&hd, host_buf, sizeof hd);
+  if (hd.magic != kMagic || hd.nx != h->G.nx || hd.ny != h->G.ny || hd.nz != h->G.nz || hd.prec != h->prec ||
+      hd.mode != h->mode || hd.f_bytes != h->plan.f || hd.g_bytes != h->plan.g || hd.phiu_bytes != h->plan.phiu)
+    return fail(h, MPLB_E_INVAL, "checkpoint does not match this lattice");
+  if (!h->have_params) return fail(h, MPLB_E_STATE, "restore before set_params");
+  const char* p = (const char*)host_buf + sizeof hd;
+  h->cur = 0;
+  HIPCHK(h, hipMemcpyAsync(h->B.f[0], p, h->plan.f, hipMemcpyHostToDevice, h->stream));
+  p += h->plan.f;
+  if (h->plan.g) HIPCHK(h, hipMemcpyAsync(h->B.g[0], p, h->plan.g, hipMemcpyHostToDevice, h->stream));
+  p += h->plan.g;
+  HIPCHK(h, hipMemcpyAsync(h->B.phiu, p, h->plan.phiu, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(h, launch_fill_int(h->B.flag, 0, 1, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->step = (long)hd.step;
+  h->have_init = true;
+  return MPLB_OK;
+}
+
+int mplb_poke(mplb_t* h, int set, int i, long node, double value) {
+  if (!h || set < 0 || set > 1 || i < 0 || node < 0 || node >= h->G.N) return MPLB_E_INVAL;
+  if ((set == 0 && i > 6) || (set == 1 && (i > 14 || h->mode != MPLB_COUPLED))) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "poke before init");
+  HIPCHK(h, launch_poke(h->prec, h->G, h->B, h->cur, set, i, (int)node, value, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MPLB_OK;
+}
+
+}  // extern "C"

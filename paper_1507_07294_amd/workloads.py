@@ -180,7 +180,13 @@ def perturbed_case(shape, bc, seed, coupled=True, ratio=3.0, sigma=0.01, D=4.0, 
         u0[2][-1] = 0.0
     sf = tuple(float(v) for v in (rng.uniform(0.8, 1.6), *([rng.uniform(0.9, 1.5)] * 3),
                                    rng.uniform(0.8, 1.6), rng.uniform(0.8, 1.6), rng.uniform(0.8, 1.6)))
-    lam = tuple(float(v) for v in rng.uniform(0.8, 1.6, size=15))
+    # S^g: the rates of the conserved-like and energy moments (0, 1, 2) stay
+    # near 1 (the paper sets them to 1; far from 1 the scheme is unstable),
+    # the others vary over (0.8, 1.6); 9..13 are set from nu anyway
+    lam = rng.uniform(0.8, 1.6, size=15)
+    lam[0] = rng.uniform(1.0, 1.2)
+    lam[1:3] = rng.uniform(0.9, 1.15, size=2)
+    lam = tuple(float(v) for v in lam)
     p = ModelParams(sigma=sigma, width=D, rho_l=ratio, rho_g=1.0, mobility=mobility, s_f=sf, nu=nu,
                     lambda_g=lam, gravity=gravity if coupled else (0.0, 0.0, 0.0), rho_ref=0.0)
     return Workload(f"perturbed_{nx}x{ny}x{nz}_s{seed}", shape, bc, coupled, p, phi, u0=u0)

@@ -1,0 +1,62 @@
+"""The C-ABI library loads and exports every entry point its header declares
+(CPU only: no call here touches a GPU)."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_1507_07294_amd import mplb
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(mplb.LIB_PATH):
+        from paper_1507_07294_amd import build
+        build.build()
+    return mplb.lib()
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = mplb.declared_symbols()
+    assert len(declared) >= 18
+    out = subprocess.run(["nm", "-D", "--defined-only", mplb.LIB_PATH], capture_output=True, text=True, check=True)
+    exported = {line.split()[-1] for line in out.stdout.splitlines() if " T " in line}
+    missing = [s for s in declared if s not in exported]
+    assert not missing, missing
+    for s in declared:
+        assert hasattr(lib, s)
+
+
+def test_host_only_calls(lib):
+    assert lib.mplb_strerror(mplb.MPLB_E_NONFINITE).decode() == "non-finite population"
+    n = C.c_size_t(0)
+    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F64, mplb.MPLB_COUPLED, C.byref(n)) == 0
+    # two time levels of 22 FP64 populations plus history, phi, mu, read-out
+    assert n.value >= 32 ** 3 * 8 * (2 * 22 + 3 + 2 + 1)
+    m = C.c_size_t(0)
+    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F32_F16, mplb.MPLB_COUPLED, C.byref(m)) == 0
+    assert m.value < n.value / 2
+    assert lib.mplb_required_bytes(0, 32, 32, mplb.MPLB_F64, mplb.MPLB_COUPLED, C.byref(n)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_required_bytes(32, 32, 32, 7, mplb.MPLB_COUPLED, C.byref(n)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_required_bytes(1 << 11, 1 << 11, 1 << 11, 0, 0, C.byref(n)) == mplb.MPLB_E_INVAL
+
+
+def test_invalid_create_is_rejected_before_any_device_call(lib):
+    h = C.c_void_p(1)
+    bc = (C.c_int * 3)(0, 0, 5)
+    assert lib.mplb_create(4, 4, 4, bc, 0, 0, None, 0, C.byref(h)) == mplb.MPLB_E_INVAL
+    assert h.value is None
+    bc = (C.c_int * 3)(0, 0, 1)
+    assert lib.mplb_create(4, -1, 4, bc, 0, 0, None, 0, C.byref(h)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_create(4, 4, 4, bc, 0, 9, None, 0, C.byref(h)) == mplb.MPLB_E_INVAL
+
+
+def test_product_path_has_no_cpu_fallback():
+    """The binding never imports the oracle and refuses to run without a GPU."""
+    src = open(mplb.__file__).read()
+    assert "oracle" not in src.replace("no CPU fallback", "")
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(RuntimeError):
+            mplb.Lattice((4, 4, 4))

@@ -1,0 +1,164 @@
+"""GPU parity: the HIP library (through its C-ABI) against the FP64 oracle on
+the same seeded inputs.  Tolerances are relative L2 per field,
+||gpu - oracle|| / max(||oracle||, floor sqrt(N)) with the floors of
+helpers.FLOORS (1e-6 for phi, rho, u; 1e-5 for p; 1e-8 for mu; lattice units):
+  FP64 compute: 1e-12 for every field (stated target of the FP64 variant).
+  FP32 compute: phi, rho 1e-5; u, p 5e-5; mu 2e-4 (mu is a difference of
+  nearly equal terms away from the interface).
+  FP16 / BF16 population storage: 5e-3 / 5e-2 on every field.
+The measured errors are printed for every case."""
+import numpy as np
+import pytest
+
+import helpers
+from paper_1507_07294_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = {"phi": 1e-5, "rho": 1e-5, "mu": 2e-4, "ux": 5e-5, "uy": 5e-5, "uz": 5e-5, "p": 5e-5}
+
+
+def _compare(w, steps, precision, tol, coupled=True):
+    print(f"\n[case] {w.name} shape={w.shape} bc={w.bc} steps={steps} prec={precision}", flush=True)
+    o = helpers.oracle_for(w)
+    g = helpers.gpu_for(w, precision)
+    done = 0
+    for s in steps:
+        o.step(s - done)
+        g.step(s - done)
+        done = s
+        ref = helpers.fields_of(o, coupled)
+        got = helpers.fields_of(g, coupled)
+        errs = helpers.rel_errors(got, ref)
+        print(f"  n={s} " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for k, e in errs.items():
+            t = tol[k] if isinstance(tol, dict) else tol
+            assert e <= t, (k, s, e)
+    return o, g
+
+
+def test_static_droplet_f64_500_steps():
+    """32^3 periodic static droplet, FP64, 500 steps: every field within 1e-12
+    of the oracle, and sum phi conserved."""
+    w = wl.static_droplet()
+    o, g = _compare(w, [1, 10, 500], "f64", F64_TOL)
+    t0 = np.abs(w.phi0).sum()
+    assert abs(g.totals()[0] - o.totals()[0]) < 1e-12 * t0
+
+
+@pytest.mark.parametrize("shape,bc,seed", [
+    ((24, 20, 18), (0, 0, 1), 1),   # odd box, walls in z
+    ((70, 37, 29), (0, 0, 1), 2),   # several 256-node blocks and a ragged tail
+    ((33, 5, 40), (0, 0, 0), 3),    # fully periodic, thin in y
+    ((9, 10, 11), (1, 1, 1), 4),    # walls on every axis
+    ((1, 1, 48), (0, 0, 1), 5),     # one column
+    ((3, 4, 1), (0, 0, 1), 6),      # one layer between walls
+    ((1, 1, 1), (0, 0, 0), 7),      # a single periodic node
+])
+def test_coupled_f64(shape, bc, seed):
+    w = wl.perturbed_case(shape, bc, seed, coupled=True, ratio=(2.5, 4.0, 7.0)[seed % 3])
+    _compare(w, [1, 10, 60], "f64", F64_TOL)
+
+
+@pytest.mark.parametrize("shape,bc,seed", [((24, 20, 18), (0, 0, 1), 11), ((70, 37, 29), (0, 0, 1), 12)])
+def test_coupled_f32(shape, bc, seed):
+    w = wl.perturbed_case(shape, bc, seed, coupled=True)
+    _compare(w, [1, 10, 100], "f32", F32_TOL)
+
+
+@pytest.mark.parametrize("kind", ["field", "zalesak", "deformation"])
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_che_only(kind, precision, tol):
+    shape, bc = (30, 26, 22), (0, 0, 0)
+    w = wl.perturbed_case(shape, bc, 21, coupled=False)
+    rng = np.random.default_rng(8)
+    if kind == "field":
+        w.velocity = {"kind": "field", "field": wl.smooth_field(shape, rng, 0.03, components=3)}
+    elif kind == "zalesak":
+        w.velocity = {"kind": "zalesak", "U": 0.02}
+    else:
+        w.velocity = {"kind": "deformation", "U": 0.02, "T": 0.05}
+    _compare(w, [1, 7, 40], precision, tol, coupled=False)
+
+
+def test_totals_match_oracle():
+    w = wl.perturbed_case((17, 19, 23), (0, 0, 0), 31, coupled=True, gravity=(1e-5, 0, -2e-5))
+    o = helpers.oracle_for(w)
+    g = helpers.gpu_for(w, "f64")
+    for _ in range(3):
+        to, tg = o.totals(), g.totals()
+        assert np.allclose(tg, to, rtol=1e-12, atol=1e-15), (tg, to)
+        # momentum balance of the GPU itself: sum j(n+1) = sum j(n) + sum F(n)
+        g.step(1)
+        o.step(1)
+        assert np.allclose(g.totals()[1:4], tg[1:4] + tg[4:7], rtol=0, atol=1e-13)
+
+
+def test_nonfinite_reported_with_step_index():
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((12, 10, 8), (0, 0, 1), 41, coupled=True)
+    g = helpers.gpu_for(w, "f64")
+    g.set_check_interval(1)
+    g.step(2)
+    g.poke(1, 3, 5 + 12 * 4, float("nan"))
+    rc, msg = g.try_step(5)
+    assert rc == mplb.MPLB_E_NONFINITE
+    assert "after step 3" in msg
+    rc, _ = g.try_totals()
+    assert rc == mplb.MPLB_E_NONFINITE
+
+
+def test_checkpoint_restore_is_bitwise():
+    w = wl.perturbed_case((20, 18, 16), (0, 0, 1), 51, coupled=True)
+    a = helpers.gpu_for(w, "f32")
+    a.step(7)
+    buf = a.checkpoint()
+    a.step(13)
+    ref = helpers.fields_of(a)
+    b = helpers.gpu_for(w, "f32")
+    b.restore(buf)
+    assert b.step_count == 7
+    b.step(13)
+    got = helpers.fields_of(b)
+    for k in ref:
+        assert np.array_equal(ref[k], got[k]), k
+
+
+def test_runs_are_deterministic():
+    w = wl.perturbed_case((40, 30, 20), (0, 0, 1), 61, coupled=True)
+    a = helpers.gpu_for(w, "f32")
+    b = helpers.gpu_for(w, "f32")
+    a.step(25)
+    b.step(25)
+    fa, fb = helpers.fields_of(a), helpers.fields_of(b)
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_step_many_equals_single_runs():
+    from paper_1507_07294_amd import mplb
+    ws = [wl.perturbed_case(s, (0, 0, 1), 70 + i, coupled=True) for i, s in
+          enumerate([(16, 16, 16), (24, 12, 20), (9, 31, 14)])]
+    alone = []
+    for w in ws:
+        g = helpers.gpu_for(w, "f32")
+        g.step(12)
+        alone.append(helpers.fields_of(g))
+    mix = [helpers.gpu_for(w, "f32") for w in ws]
+    mplb.mplb_step_many(mix, 12)
+    for g, ref in zip(mix, alone):
+        got = helpers.fields_of(g)
+        for k in ref:
+            assert np.array_equal(ref[k], got[k]), k
+
+
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+def test_storage_precision_error(precision):
+    """16-bit population storage (f_0 and the history stay FP32): the error
+    against the FP64 oracle after 200 steps of a perturbed droplet between
+    walls is reported; the bound is 5e-3 (FP16) and 5e-2 (BF16) relative L2
+    on every field."""
+    w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 81, coupled=True)
+    tol = 5e-3 if precision == "f16" else 5e-2
+    _compare(w, [1, 10, 100, 200], precision, tol)
