@@ -155,8 +155,9 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes);
 
 /* Measurement: advance nsteps steps with HIP events recorded on the handle's
  * stream around each kernel stage; ms[0..3] receive the summed durations of
- * the phi pass, the mu pass, the collide-and-stream kernel and the whole
- * steps.  Synchronises; the state advances exactly as with mplb_step. */
+ * a separate phi pass, a separate mu pass (both 0 when, as now, one kernel
+ * does the whole step), the collide-and-stream kernel and the whole steps.
+ * Synchronises; the state advances exactly as with mplb_step. */
 int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
 
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;

@@ -12,8 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmplb.so")
-SOURCES = ["kernels.hip", "mplb.cpp"]
-HEADERS = ["common.h", "launch.h"]
+SOURCES = ["kernels.hip", "fused.hip", "mplb.cpp"]
+HEADERS = ["common.h", "device.h", "launch.h"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

@@ -1,0 +1,455 @@
+// One-kernel time step of the 3D MRT phase-field lattice-Boltzmann model
+// (coupled D3Q7 + D3Q15, and the CHE-only D3Q7 variant), z-marching with
+// LDS rings.
+//
+// A block owns a 64 x TY column of nodes and marches along z through a
+// segment [z0, z1).  At plane z it
+//   (a) pulls the seven f populations of plane z+2 on the tile plus a halo of
+//       two nodes and sums them into phi (Eq. 13) in an LDS ring of 5 planes,
+//   (b) evaluates mu (Eqs. 2, 36) of plane z+1 on the tile plus a halo of one
+//       into an LDS ring of 3 planes,
+//   (c) finishes the nodes of plane z: grad phi and lap mu (Eqs. 35-36) from
+//       LDS, pulls f and g, forms u, p and the forces (Eqs. 29-30),
+//       d_t(phi u) (Eq. 34), collides both lattices in moment space and
+//       stores f*, g* and (phi u).
+// Each stored population is pulled from HBM by the tile that owns its
+// destination; the halo pulls of (a) and the second pull of the tile's own f
+// in (c) re-read data that blocks running together on one XCD share through
+// its L2 (the block order is remapped so that each XCD gets a contiguous run
+// of tiles).
+//
+// Index arithmetic is hoisted out of the z loop: a thread's x and y source
+// offsets (with periodic wrap) are fixed for the whole march, and the plane
+// offsets and the bounce-back decisions of a z wall are uniform over the
+// block.  Walls on the x or y axis are handled by a separate instantiation.
+//
+// Finite-difference ghosts: phi beyond a wall is the mirror phi(-1) = phi(0);
+// mu at a ghost position is evaluated at its mirror image, so mu(-1) = mu(0).
+#include "common.h"
+#include "device.h"
+#include "launch.h"
+
+namespace mplb {
+namespace {
+
+using namespace dev;
+
+constexpr int kTX = 64;
+
+// Block -> logical tile with a contiguous run of tiles per XCD (workgroups
+// are dispatched round-robin over the 8 XCDs).
+__device__ inline int logical_block(int b, int nb) {
+  const int X = 8;
+  int per = nb / X, rem = nb % X;
+  int xcd = b % X, k = b / X;
+  return (xcd < rem) ? xcd * (per + 1) + k : rem * (per + 1) + (xcd - rem) * per + k;
+}
+
+// periodic wrap, or clamp onto the wall layer (mirror ghost of phi)
+__device__ inline int map_axis(int v, int n, int wall) {
+  if (wall) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+  v %= n;
+  return v < 0 ? v + n : v;
+}
+__device__ inline int clamp_axis(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+__device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+struct Tiling {
+  int tiles_x, tiles_y, lz, nseg;
+};
+
+// Source offsets of one lattice column (x, y): for a velocity component c in
+// {-1, 0, 1}, xs[c+1] is the source x (x - c, wrapped) and xb[c+1] says the
+// population comes through an x wall; ys holds y * nx likewise.
+struct Column {
+  int xs[3], ys[3];
+  bool xb[3], yb[3];
+};
+
+template <bool XYWALL>
+__device__ inline Column make_column(const Geo& G, int x, int y) {
+  Column c;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int sx = x - (k - 1), sy = y - (k - 1);
+    c.xb[k] = XYWALL && G.wall_x && (sx < 0 || sx >= G.nx);
+    c.yb[k] = XYWALL && G.wall_y && (sy < 0 || sy >= G.ny);
+    c.xs[k] = wrap1(sx, G.nx);
+    c.ys[k] = wrap1(sy, G.ny) * G.nx;
+  }
+  return c;
+}
+
+// Plane offsets for the sources of plane z (z - cz) and the z-wall bounce,
+// uniform over the block.
+struct Plane {
+  int zs[3];
+  bool zb[3];
+  int z;
+};
+
+__device__ inline Plane make_plane(const Geo& G, int z) {
+  Plane p;
+  p.z = z;
+  const int nxy = G.nx * G.ny;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    int sz = z - (k - 1);
+    p.zb[k] = G.wall_z && (sz < 0 || sz >= G.nz);
+    p.zs[k] = wrap1(sz, G.nz) * nxy;
+  }
+  return p;
+}
+
+// Pull the populations of lattice Q (7 or 15) into node (column c, plane p).
+template <int P, int Q, bool XYWALL, bool IS_F>
+__device__ inline void pull_col(const Geo& G, const void* base, const Column& c, const Plane& p, int self,
+                                typename Prec<P>::T* v) {
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int cx = Q == 7 ? c7(i, 0) : c15(i, 0), cy = Q == 7 ? c7(i, 1) : c15(i, 1),
+              cz = Q == 7 ? c7(i, 2) : c15(i, 2);
+    bool b = p.zb[cz + 1];
+    if (XYWALL) b = b || c.xb[cx + 1] || c.yb[cy + 1];
+    int src = p.zs[cz + 1] + c.ys[cy + 1] + c.xs[cx + 1];
+    int k = b ? opp(i) : i;
+    int idx = b ? self : src;
+    if (IS_F) v[i] = Lat<P>::ldf(base, G.pitch, k, idx);
+    else v[i] = Lat<P>::ldg(base, G.pitch, k, idx);
+  }
+}
+
+// Eq. 36 at a ring position c of the middle plane pc, with the planes below
+// (pm) and above (pp); 2/3 per face and 1/12 per corner.
+template <class T, int PX>
+__device__ inline T lap_lds(const T* pm, const T* pc, const T* pp, int c) {
+  T c0 = pc[c];
+  T lf = ((pc[c - 1] - c0) + (pc[c + 1] - c0)) + ((pc[c - PX] - c0) + (pc[c + PX] - c0)) + ((pm[c] - c0) + (pp[c] - c0));
+  T lc = ((pm[c - PX - 1] - c0) + (pm[c - PX + 1] - c0)) + ((pm[c + PX - 1] - c0) + (pm[c + PX + 1] - c0)) +
+         ((pp[c - PX - 1] - c0) + (pp[c - PX + 1] - c0)) + ((pp[c + PX - 1] - c0) + (pp[c + PX + 1] - c0));
+  return (T)(2.0 / 3.0) * lf + (T)(1.0 / 12.0) * lc;
+}
+
+// Eq. 35: face neighbours weigh 1/3, corners 1/24.
+template <class T, int PX>
+__device__ inline void grad_lds(const T* pm, const T* pc, const T* pp, int c, T gr[3]) {
+  T a = pm[c + PX + 1], b = pm[c + PX - 1], d = pm[c - PX + 1], e = pm[c - PX - 1];
+  T A = pp[c + PX + 1], Bv = pp[c + PX - 1], D = pp[c - PX + 1], E = pp[c - PX - 1];
+  T cx = ((a - b) + (d - e)) + ((A - Bv) + (D - E));
+  T cy = ((a - d) + (b - e)) + ((A - D) + (Bv - E));
+  T cz = ((A - a) + (Bv - b)) + ((D - d) + (E - e));
+  gr[0] = (T)(1.0 / 3.0) * (pc[c + 1] - pc[c - 1]) + (T)(1.0 / 24.0) * cx;
+  gr[1] = (T)(1.0 / 3.0) * (pc[c + PX] - pc[c - PX]) + (T)(1.0 / 24.0) * cy;
+  gr[2] = (T)(1.0 / 3.0) * (pp[c] - pm[c]) + (T)(1.0 / 24.0) * cz;
+}
+
+template <int P, int TY, int HALO>
+struct Ring {
+  static constexpr int NT = kTX * TY;
+  static constexpr int PX = kTX + 2 * HALO, PY = TY + 2 * HALO;
+  static constexpr int NPHI = PX * PY;
+  static constexpr int NHALO = NPHI - NT;
+  static constexpr int HPT = (NHALO + NT - 1) / NT;  // halo positions per thread
+};
+
+// Halo position h of a (PX x PY) padded tile with a halo of H: H rows on each
+// side in y, then H columns on each side in x for the interior rows.
+template <int PX, int PY, int H>
+__device__ inline void halo_pos(int h, int& px, int& py) {
+  if (h < H * PX) { py = h / PX; px = h % PX; return; }
+  h -= H * PX;
+  if (h < H * PX) { py = PY - H + h / PX; px = h % PX; return; }
+  h -= H * PX;
+  py = H + h / (2 * H);
+  int c = h % (2 * H);
+  px = c < H ? c : PX - 2 * H + c;
+}
+
+// Per-thread phi-load positions: the own tile node plus up to HPT halo nodes,
+// each as an LDS slot and the source columns of its seven f pulls.
+template <int P, int TY, int HALO, bool XYWALL>
+struct PhiLoader {
+  using R = Ring<P, TY, HALO>;
+  Column own;
+  int own_lds;
+  Column halo[R::HPT];
+  int halo_lds[R::HPT];
+  bool halo_on[R::HPT];
+  int own_xy, halo_xy[R::HPT];  // x + nx*y of the (mapped) node
+
+  __device__ void init(const Geo& G, int x0, int y0) {
+    const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+    int mx = map_axis(x0 + tx, G.nx, G.wall_x), my = map_axis(y0 + ty, G.ny, G.wall_y);
+    own = make_column<XYWALL>(G, mx, my);
+    own_xy = mx + G.nx * my;
+    own_lds = (ty + HALO) * R::PX + tx + HALO;
+#pragma unroll
+    for (int k = 0; k < R::HPT; ++k) {
+      int h = threadIdx.x + k * R::NT;
+      halo_on[k] = h < R::NHALO;
+      int px = 0, py = 0;
+      if (halo_on[k]) halo_pos<R::PX, R::PY, HALO>(h, px, py);
+      int hx = map_axis(x0 - HALO + px, G.nx, G.wall_x), hy = map_axis(y0 - HALO + py, G.ny, G.wall_y);
+      halo[k] = make_column<XYWALL>(G, hx, hy);
+      halo_xy[k] = hx + G.nx * hy;
+      halo_lds[k] = py * R::PX + px;
+    }
+  }
+
+  // phi of logical plane zl (mapped onto the lattice) into ring slot s
+  __device__ void load(const Geo& G, const void* fin, int zl, typename Prec<P>::T* s) {
+    using T = typename Prec<P>::T;
+    int mz = map_axis(zl, G.nz, G.wall_z);
+    Plane p = make_plane(G, mz);
+    int zo = mz * G.nx * G.ny;
+    T f[7];
+    pull_col<P, 7, XYWALL, true>(G, fin, own, p, zo + own_xy, f);
+    s[own_lds] = phi_of(f);
+#pragma unroll
+    for (int k = 0; k < R::HPT; ++k) {
+      if (halo_on[k]) {
+        pull_col<P, 7, XYWALL, true>(G, fin, halo[k], p, zo + halo_xy[k], f);
+        s[halo_lds[k]] = phi_of(f);
+      }
+    }
+  }
+};
+
+// Per-thread mu positions on the tile + halo 1 (mirror images for walls).
+template <int P, int TY>
+struct MuMaker {
+  using R2 = Ring<P, TY, 2>;
+  static constexpr int QX = kTX + 2, QY = TY + 2, NMU = QX * QY;
+  static constexpr int MPT = (NMU + R2::NT - 1) / R2::NT;
+  int src[MPT];  // phi ring slot index of the position (or its mirror)
+  int dst[MPT];
+  bool on[MPT];
+
+  __device__ void init(const Geo& G, int x0, int y0) {
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      int q = threadIdx.x + k * R2::NT;
+      on[k] = q < NMU;
+      int qx = q % QX, qy = q / QX;
+      int gx = x0 - 1 + qx, gy = y0 - 1 + qy;
+      if (G.wall_x) gx = clamp_axis(gx, G.nx);
+      if (G.wall_y) gy = clamp_axis(gy, G.ny);
+      src[k] = (gy - (y0 - 2)) * R2::PX + (gx - (x0 - 2));
+      dst[k] = q;
+    }
+  }
+
+  __device__ void run(const Geo& G, const Coef<typename Prec<P>::T>& C, int zl,
+                      typename Prec<P>::T (*sphi)[R2::NPHI], typename Prec<P>::T* smu) {
+    using T = typename Prec<P>::T;
+    int ze = G.wall_z ? clamp_axis(zl, G.nz) : zl;
+    const T* pm = sphi[(ze - 1 + 10) % 5];
+    const T* pc = sphi[(ze + 10) % 5];
+    const T* pp = sphi[(ze + 1 + 10) % 5];
+#pragma unroll
+    for (int k = 0; k < MPT; ++k) {
+      if (on[k]) {
+        T c0 = pc[src[k]];
+        T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k]);
+        smu[dst[k]] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
+      }
+    }
+  }
+};
+
+// at least 4 waves per SIMD for FP32 compute (<= 128 VGPRs), 2 for FP64
+template <int P>
+constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
+
+template <int P, int TY, bool XYWALL>
+__global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
+k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+  using T = typename Prec<P>::T;
+  using R = Ring<P, TY, 2>;
+  using MU = MuMaker<P, TY>;
+  __shared__ T sphi[5][R::NPHI];
+  __shared__ T smu[3][MU::NMU];
+  const int lb = logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
+  const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
+  const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx < G.nx && gy < G.ny;
+  const void* fin = B.f[cur];
+  const void* gin = B.g[cur];
+  void* fo = B.f[1 - cur];
+  void* go = B.g[1 - cur];
+  T* hist = (T*)B.phiu;
+
+  PhiLoader<P, TY, 2, XYWALL> ld;
+  ld.init(G, x0, y0);
+  MU mm;
+  mm.init(G, x0, y0);
+  const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
+  const int col_xy = gx + G.nx * gy;
+  const int lds_c = (ty + 2) * R::PX + tx + 2;
+  const int mu_c = (ty + 1) * MU::QX + tx + 1;
+
+  // warm-up: phi planes z0-2 .. z0+1, mu planes z0-1, z0
+  for (int zl = z0 - 2; zl <= z0 + 1; ++zl) ld.load(G, fin, zl, sphi[(zl + 10) % 5]);
+  __syncthreads();
+  mm.run(G, C, z0 - 1, sphi, smu[(z0 - 1 + 6) % 3]);
+  mm.run(G, C, z0, sphi, smu[(z0 + 6) % 3]);
+
+  for (int z = z0; z < z1; ++z) {
+    ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5]);
+    __syncthreads();
+    mm.run(G, C, z + 1, sphi, smu[(z + 1 + 6) % 3]);
+    __syncthreads();
+    if (!own) continue;
+    const int n = z * G.nx * G.ny + col_xy;
+    const Plane p = make_plane(G, z);
+    T f[7], g[15];
+    pull_col<P, 7, XYWALL, true>(G, fin, col, p, n, f);
+    pull_col<P, 15, XYWALL, false>(G, gin, col, p, n, g);
+    T phi = phi_of(f);
+    T gphi[3];
+    grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi);
+    const T* mc = smu[(z + 6) % 3];
+    T mu = mc[mu_c];
+    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c);
+    Macro<T> M;
+    flow_macro(C, g, phi, mu, gphi, lapmu, M);
+    T dphiu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T pu = phi * M.u[a];
+      dphiu[a] = pu - hist[(size_t)a * G.pitch + n];
+      hist[(size_t)a * G.pitch + n] = pu;
+    }
+    collide_che(C, f, phi, mu, M.u, dphiu);
+    collide_ns(C, g, M);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
+#pragma unroll
+    for (int i = 0; i < 15; ++i) Lat<P>::stg(go, G.pitch, i, n, g[i]);
+    if (!(all_finite(f, 7) && all_finite(g, 15))) *B.flag = 1;
+  }
+}
+
+// CHE-only: mu is needed at the node only, so phi needs a halo of one and a
+// ring of 4 planes (plane z+1 is loaded while plane z is finished).
+template <int P, int TY, bool XYWALL>
+__global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
+k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+  using T = typename Prec<P>::T;
+  using R = Ring<P, TY, 1>;
+  __shared__ T sphi[4][R::NPHI];
+  const int lb = logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
+  const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
+  const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int gx = x0 + tx, gy = y0 + ty;
+  const bool own = gx < G.nx && gy < G.ny;
+  const void* fin = B.f[cur];
+  void* fo = B.f[1 - cur];
+  T* hist = (T*)B.phiu;
+  PhiLoader<P, TY, 1, XYWALL> ld;
+  ld.init(G, x0, y0);
+  const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
+  const int col_xy = gx + G.nx * gy;
+  const int lds_c = (ty + 1) * R::PX + tx + 1;
+  ld.load(G, fin, z0 - 1, sphi[(z0 - 1 + 8) % 4]);
+  ld.load(G, fin, z0, sphi[(z0 + 8) % 4]);
+  for (int z = z0; z < z1; ++z) {
+    ld.load(G, fin, z + 1, sphi[(z + 1 + 8) % 4]);
+    __syncthreads();
+    if (!own) continue;
+    const int n = z * G.nx * G.ny + col_xy;
+    const Plane p = make_plane(G, z);
+    T f[7];
+    pull_col<P, 7, XYWALL, true>(G, fin, col, p, n, f);
+    T phi = phi_of(f);
+    T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c);
+    T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
+    T u[3];
+    presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u);
+    T dphiu[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      T pu = phi * u[a];
+      dphiu[a] = pu - hist[(size_t)a * G.pitch + n];
+      hist[(size_t)a * G.pitch + n] = pu;
+    }
+    collide_che(C, f, phi, mu, u, dphiu);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
+    if (!all_finite(f, 7)) *B.flag = 1;
+  }
+}
+
+template <class T>
+Coef<T> cast_coef_f(const Coef<double>& c) {
+  Coef<T> o;
+  o.rho_l = (T)c.rho_l; o.rho_g = (T)c.rho_g; o.drho = (T)c.drho;
+  o.beta = (T)c.beta; o.kappa = (T)c.kappa; o.eta = (T)c.eta; o.A = (T)c.A; o.mob = (T)c.mob;
+  o.rho_ref = (T)c.rho_ref;
+  for (int a = 0; a < 3; ++a) o.grav[a] = (T)c.grav[a];
+  for (int i = 0; i < 7; ++i) o.sf[i] = (T)c.sf[i];
+  for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
+  o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct;
+  return o;
+}
+
+#ifndef MPLB_TILE_Y
+#define MPLB_TILE_Y 8
+#endif
+constexpr int kTY = MPLB_TILE_Y;
+
+// Segment length along z: enough blocks to fill the chip several times over,
+// but long segments where possible (each segment re-reads a few planes).
+Tiling make_tiling(const Geo& G, int TY, int min_lz) {
+  Tiling t;
+  t.tiles_x = (G.nx + kTX - 1) / kTX;
+  t.tiles_y = (G.ny + TY - 1) / TY;
+  int cols = t.tiles_x * t.tiles_y;
+  int want = (2048 + cols - 1) / cols;
+  int lz = (G.nz + want - 1) / want;
+  if (lz < min_lz) lz = min_lz;
+  if (lz > G.nz) lz = G.nz;
+  t.lz = lz;
+  t.nseg = (G.nz + lz - 1) / lz;
+  return t;
+}
+
+template <int P, bool XYWALL>
+hipError_t fused_impl2(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
+                       hipStream_t s) {
+  Tiling tl = make_tiling(G, kTY, 16);
+  dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
+  if (mode == MPLB_COUPLED)
+    hipLaunchKernelGGL((k_fused<P, kTY, XYWALL>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+  else
+    hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t fused_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur, hipStream_t s) {
+  using T = typename Prec<P>::T;
+  Coef<T> C = cast_coef_f<T>(Cd);
+  if (G.wall_x || G.wall_y) return fused_impl2<P, true>(mode, G, C, B, cur, s);
+  return fused_impl2<P, false>(mode, G, C, B, cur, s);
+}
+
+}  // namespace
+
+hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                             hipStream_t s) {
+  switch (P) {
+    case MPLB_F64: return fused_impl<MPLB_F64>(mode, G, C, B, cur, s);
+    case MPLB_F32: return fused_impl<MPLB_F32>(mode, G, C, B, cur, s);
+    case MPLB_F32_F16: return fused_impl<MPLB_F32_F16>(mode, G, C, B, cur, s);
+    case MPLB_F32_BF16: return fused_impl<MPLB_F32_BF16>(mode, G, C, B, cur, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace mplb

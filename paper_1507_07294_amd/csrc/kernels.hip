@@ -17,323 +17,13 @@
 #include <cmath>
 
 #include "common.h"
+#include "device.h"
 #include "launch.h"
 
 namespace mplb {
 namespace {
 
-// ---------------------------------------------------------------- lattices
-// D3Q15 velocities in the order of Eq. 23; D3Q7 in the order of Eq. 6.
-__host__ __device__ constexpr int c15(int i, int a) {
-  constexpr int t[15][3] = {{0, 0, 0},   {1, 0, 0},   {-1, 0, 0},  {0, 1, 0},  {0, -1, 0},
-                            {0, 0, 1},   {0, 0, -1},  {1, 1, 1},   {-1, -1, -1}, {1, 1, -1},
-                            {-1, -1, 1}, {1, -1, 1},  {-1, 1, -1}, {1, -1, -1}, {-1, 1, 1}};
-  return t[i][a];
-}
-__host__ __device__ constexpr int c7(int i, int a) {
-  constexpr int t[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
-  return t[i][a];
-}
-// both lattices list velocities in antipodal pairs (1,2), (3,4), ...
-__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
-
-// ---------------------------------------------------------------- storage
-template <int P>
-struct Lat {
-  using T = typename Prec<P>::T;
-  using S0 = typename Prec<P>::S0;
-  using S = typename Prec<P>::S;
-  __device__ static const S0* f0(const void* base) { return (const S0*)base; }
-  __device__ static S0* f0(void* base) { return (S0*)base; }
-  __device__ static const S* fi(const void* base, int pitch) { return (const S*)((const char*)base + (size_t)pitch * sizeof(S0)); }
-  __device__ static S* fi(void* base, int pitch) { return (S*)((char*)base + (size_t)pitch * sizeof(S0)); }
-  __device__ static T ldf(const void* base, int pitch, int i, int n) {
-    return i == 0 ? (T)f0(base)[n] : (T)fi(base, pitch)[(size_t)(i - 1) * pitch + n];
-  }
-  __device__ static void stf(void* base, int pitch, int i, int n, T v) {
-    if (i == 0) f0(base)[n] = (S0)v;
-    else fi(base, pitch)[(size_t)(i - 1) * pitch + n] = (S)v;
-  }
-  __device__ static T ldg(const void* base, int pitch, int i, int n) { return (T)((const S*)base)[(size_t)i * pitch + n]; }
-  __device__ static void stg(void* base, int pitch, int i, int n, T v) { ((S*)base)[(size_t)i * pitch + n] = (S)v; }
-};
-
-// ---------------------------------------------------------------- geometry
-__device__ inline void decode(const Geo& G, int n, int& x, int& y, int& z) {
-  x = n % G.nx;
-  int t = n / G.nx;
-  y = t % G.ny;
-  z = t / G.ny;
-}
-
-// Source node of a population with velocity (cx,cy,cz) arriving at (x,y,z),
-// or -1 if it left through a wall (then it is the opposite population of
-// (x,y,z) reflected back).
-__device__ inline int pull_src(const Geo& G, int x, int y, int z, int cx, int cy, int cz) {
-  int sx = x - cx, sy = y - cy, sz = z - cz;
-  if (sx < 0) { if (G.wall_x) return -1; sx += G.nx; } else if (sx >= G.nx) { if (G.wall_x) return -1; sx -= G.nx; }
-  if (sy < 0) { if (G.wall_y) return -1; sy += G.ny; } else if (sy >= G.ny) { if (G.wall_y) return -1; sy -= G.ny; }
-  if (sz < 0) { if (G.wall_z) return -1; sz += G.nz; } else if (sz >= G.nz) { if (G.wall_z) return -1; sz -= G.nz; }
-  return sx + G.nx * (sy + G.ny * sz);
-}
-
-// Neighbour for the finite differences: periodic wrap, or the mirror ghost
-// chi(-1) = chi(0), chi(n) = chi(n-1) on wall axes.
-__device__ inline int stencil_nb(const Geo& G, int x, int y, int z, int dx, int dy, int dz) {
-  int qx = x + dx, qy = y + dy, qz = z + dz;
-  if (qx < 0) qx = G.wall_x ? 0 : qx + G.nx; else if (qx >= G.nx) qx = G.wall_x ? G.nx - 1 : qx - G.nx;
-  if (qy < 0) qy = G.wall_y ? 0 : qy + G.ny; else if (qy >= G.ny) qy = G.wall_y ? G.ny - 1 : qy - G.ny;
-  if (qz < 0) qz = G.wall_z ? 0 : qz + G.nz; else if (qz >= G.nz) qz = G.wall_z ? G.nz - 1 : qz - G.nz;
-  return qx + G.nx * (qy + G.ny * qz);
-}
-
-template <int P>
-__device__ inline void pull_f(const Geo& G, const void* fb, int x, int y, int z, int n, typename Prec<P>::T f[7]) {
-#pragma unroll
-  for (int i = 0; i < 7; ++i) {
-    int s = (i == 0) ? n : pull_src(G, x, y, z, c7(i, 0), c7(i, 1), c7(i, 2));
-    f[i] = (s >= 0) ? Lat<P>::ldf(fb, G.pitch, i, s) : Lat<P>::ldf(fb, G.pitch, opp(i), n);
-  }
-}
-
-template <int P>
-__device__ inline void pull_g(const Geo& G, const void* gb, int x, int y, int z, int n, typename Prec<P>::T g[15]) {
-#pragma unroll
-  for (int i = 0; i < 15; ++i) {
-    int s = (i == 0) ? n : pull_src(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2));
-    g[i] = (s >= 0) ? Lat<P>::ldg(gb, G.pitch, i, s) : Lat<P>::ldg(gb, G.pitch, opp(i), n);
-  }
-}
-
-template <class T>
-__device__ inline T phi_of(const T f[7]) {
-  return f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + (f[5] + f[6]));
-}
-
-// Eq. 35 (gradient) and Eq. 36 (Laplacian) with D3Q15 weights, c_s^2 = 1/3:
-// face neighbours weigh 1/3 (gradient) and 2/3 (Laplacian), corners 1/24 and 1/12.
-template <class T>
-__device__ inline void grad_lap(const Geo& G, const T* chi, int x, int y, int z, T c0, T gr[3], T& lap,
-                                bool want_grad) {
-  T gx = 0, gy = 0, gz = 0, lf = 0, lc = 0;
-#pragma unroll
-  for (int i = 1; i < 15; ++i) {
-    T v = chi[stencil_nb(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2))];
-    if (i < 7) {
-      lf += v - c0;
-      if (want_grad) { gx += c15(i, 0) * v; gy += c15(i, 1) * v; gz += c15(i, 2) * v; }
-    } else {
-      lc += v - c0;
-      if (want_grad) {
-        gx += (T)(1.0 / 8.0) * c15(i, 0) * v;
-        gy += (T)(1.0 / 8.0) * c15(i, 1) * v;
-        gz += (T)(1.0 / 8.0) * c15(i, 2) * v;
-      }
-    }
-  }
-  lap = (T)(2.0 / 3.0) * lf + (T)(1.0 / 12.0) * lc;
-  gr[0] = gx * (T)(1.0 / 3.0);
-  gr[1] = gy * (T)(1.0 / 3.0);
-  gr[2] = gz * (T)(1.0 / 3.0);
-}
-
-// Prescribed velocity of the interface-tracking runs: a constant field,
-// Zalesak's rotation (Eq. 37) or the deformation flow (Eq. 41 times
-// cos(pi t / T), the cosine passed in as C.vel_ct).
-template <class T>
-__device__ inline void presc_u(const Geo& G, const Coef<T>& C, const T* uf, int x, int y, int z, int n, T u[3]) {
-  u[0] = u[1] = u[2] = 0;
-  if (C.vel_kind == MPLB_VEL_FIELD) {
-    u[0] = uf[n];
-    u[1] = uf[(size_t)G.pitch + n];
-    u[2] = uf[2 * (size_t)G.pitch + n];
-  } else if (C.vel_kind == MPLB_VEL_ZALESAK) {
-    const T pi = (T)3.14159265358979323846;
-    T L = (T)G.nx;
-    u[1] = (C.velU * pi / L) * (L / 2 - (T)z);
-    u[2] = (C.velU * pi / L) * ((T)y - L / 2);
-  } else if (C.vel_kind == MPLB_VEL_DEFORM) {
-    const T pi = (T)3.14159265358979323846;
-    T xh = (T)x / (T)G.nx, yh = (T)y / (T)G.ny, zh = (T)z / (T)G.nz;
-    T sx = sin(pi * xh), sy = sin(pi * yh), sz = sin(pi * zh);
-    T s2x = sin(2 * pi * xh), s2y = sin(2 * pi * yh), s2z = sin(2 * pi * zh);
-    T U = C.velU, ct = C.vel_ct;
-    u[0] = 2 * U * sx * sx * s2y * s2z * ct;
-    u[1] = -U * s2x * sy * sy * s2z * ct;
-    u[2] = -U * s2x * s2y * sz * sz * ct;
-  }
-}
-
-// ------------------------------------------------------------ node physics
-// Macroscopic state of a node at level n (coupled model).
-template <class T>
-struct Macro {
-  T phi, rho, mu, u[3], p, F[3], gr[3];
-};
-
-// u, p and the forces from pulled g, phi, mu, grad phi and lap mu (Eqs. 29-30;
-// F_s = mu grad phi, F_a = (rho_l - rho_g) M lap(mu) u / 2, G = (rho - rho_ref) g).
-template <class T>
-__device__ inline void flow_macro(const Coef<T>& C, const T g[15], T phi, T mu, const T gphi[3], T lapmu,
-                                  Macro<T>& m) {
-  m.phi = phi;
-  m.mu = mu;
-  m.rho = (1 + phi) / 2 * C.rho_l + (1 - phi) / 2 * C.rho_g;
-  T half_dr = C.drho / 2;
-  T jx = (g[1] - g[2]) + (((g[7] - g[8]) + (g[9] - g[10])) + ((g[11] - g[12]) + (g[13] - g[14])));
-  T jy = (g[3] - g[4]) + (((g[7] - g[8]) + (g[9] - g[10])) - ((g[11] - g[12]) + (g[13] - g[14])));
-  T jz = (g[5] - g[6]) + (((g[7] - g[8]) - (g[9] - g[10])) + ((g[11] - g[12]) - (g[13] - g[14])));
-  T sum_nz = ((g[1] + g[2]) + (g[3] + g[4]) + (g[5] + g[6])) +
-             (((g[7] + g[8]) + (g[9] + g[10])) + ((g[11] + g[12]) + (g[13] + g[14])));
-  T Fs[3], Gb[3], j[3] = {jx, jy, jz};
-  T ml = C.mob * lapmu;
-  T denom = m.rho - (T)0.25 * C.drho * ml;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    m.gr[a] = half_dr * gphi[a];
-    Fs[a] = mu * gphi[a];
-    Gb[a] = (m.rho - C.rho_ref) * C.grav[a];
-    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) / denom;
-    m.F[a] = Fs[a] + half_dr * ml * m.u[a] + Gb[a];
-  }
-  T uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-  T ugr = m.u[0] * m.gr[0] + m.u[1] * m.gr[1] + m.u[2] * m.gr[2];
-  // c_s^2 / (1 - w_0) = 3/7 and rho s_0(u) = -rho |u|^2 / 3 (Eq. 30)
-  m.p = (T)(3.0 / 7.0) * (sum_nz + (T)0.5 * ugr - m.rho * uu / 3);
-}
-
-// D3Q7 collision in moment space (Eqs. 15, 17, 18, 11): m = M f;
-// m* = m - S^f (m - m^eq) + (I - S^f/2) mR; f* = M^-1 m*.
-template <class T>
-__device__ inline void collide_che(const Coef<T>& C, T f[7], T phi, T mu, const T u[3], const T dphiu[3]) {
-  T s12 = f[1] + f[2], s34 = f[3] + f[4], s56 = f[5] + f[6];
-  T m1 = f[1] - f[2], m2 = f[3] - f[4], m3 = f[5] - f[6];
-  T m4 = 6 * f[0] - ((s12 + s34) + s56);
-  T m5 = 2 * s12 - (s34 + s56);
-  T m6 = s34 - s56;
-  T ms1 = m1 - C.sf[1] * (m1 - phi * u[0]) + (1 - C.sf[1] / 2) * dphiu[0];
-  T ms2 = m2 - C.sf[2] * (m2 - phi * u[1]) + (1 - C.sf[2] / 2) * dphiu[1];
-  T ms3 = m3 - C.sf[3] * (m3 - phi * u[2]) + (1 - C.sf[3] / 2) * dphiu[2];
-  T ms4 = m4 - C.sf[4] * (m4 - (6 * phi - 21 * C.A * C.eta * mu));
-  T ms5 = m5 - C.sf[5] * m5;
-  T ms6 = m6 - C.sf[6] * m6;
-  // M^-1 = M^T diag(1/7, 1/2, 1/2, 1/2, 1/42, 1/12, 1/4)
-  T b0 = phi * (T)(1.0 / 7.0), b1 = ms1 / 2, b2 = ms2 / 2, b3 = ms3 / 2;
-  T b4 = ms4 * (T)(1.0 / 42.0), b5 = ms5 * (T)(1.0 / 12.0), b6 = ms6 / 4;
-  T c = b0 - b4;
-  f[0] = b0 + 6 * b4;
-  f[1] = c + b1 + 2 * b5;
-  f[2] = c - b1 + 2 * b5;
-  f[3] = c + b2 - b5 + b6;
-  f[4] = c - b2 - b5 + b6;
-  f[5] = c + b3 - b5 - b6;
-  f[6] = c - b3 - b5 - b6;
-}
-
-// D3Q15 collision in moment space (Eqs. 20, 27, 31, 32): m = Gamma g;
-// m* = m - S^g (m - m^eq) + (I - S^g/2) mT; g* = Gamma^-1 m*.  Gamma's rows are
-// d'Humieres' basis on the Eq. 23 velocity order.
-template <class T>
-__device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) {
-  // face and corner combinations (corner pairs (7,8) (9,10) (11,12) (13,14) are antipodal)
-  T sx = g[1] + g[2], sy = g[3] + g[4], sz = g[5] + g[6];
-  T dx = g[1] - g[2], dy = g[3] - g[4], dz = g[5] - g[6];
-  T p1 = g[7] + g[8], p2 = g[9] + g[10], p3 = g[11] + g[12], p4 = g[13] + g[14];
-  T d1 = g[7] - g[8], d2 = g[9] - g[10], d3 = g[11] - g[12], d4 = g[13] - g[14];
-  T Sf = (sx + sy) + sz, Sc = (p1 + p2) + (p3 + p4);
-  T Xc = (d1 + d2) + (d3 + d4), Yc = (d1 + d2) - (d3 + d4), Zc = (d1 - d2) + (d3 - d4);
-  T m[15];
-  m[0] = g[0] + Sf + Sc;
-  m[1] = -2 * g[0] - Sf + Sc;
-  m[2] = 16 * g[0] - 4 * Sf + Sc;
-  m[3] = dx + Xc;
-  m[4] = -4 * dx + Xc;
-  m[5] = dy + Yc;
-  m[6] = -4 * dy + Yc;
-  m[7] = dz + Zc;
-  m[8] = -4 * dz + Zc;
-  m[9] = 2 * sx - (sy + sz);
-  m[10] = sy - sz;
-  m[11] = (p1 + p2) - (p3 + p4);
-  m[12] = (p1 - p2) - (p3 - p4);
-  m[13] = (p1 - p2) + (p3 - p4);
-  m[14] = (d1 - d2) - (d3 - d4);
-
-  const T* u = M.u;
-  T rho = M.rho, p = M.p;
-  T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
-  T cs2 = (T)(1.0 / 3.0);
-  T eq[15], src[15];
-  // Eq. 31
-  eq[0] = 0;
-  eq[1] = 3 * p + rho * uu;
-  eq[2] = -(45 * p + 5 * rho * uu);
-  eq[3] = rho * u[0];
-  eq[4] = -7 * rho * u[0] / 3;
-  eq[5] = rho * u[1];
-  eq[6] = -7 * rho * u[1] / 3;
-  eq[7] = rho * u[2];
-  eq[8] = -7 * rho * u[2] / 3;
-  eq[9] = rho * (2 * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
-  eq[10] = rho * (u[1] * u[1] - u[2] * u[2]);
-  eq[11] = rho * u[0] * u[1];
-  eq[12] = rho * u[1] * u[2];
-  eq[13] = rho * u[0] * u[2];
-  eq[14] = 0;
-  // Eq. 32 with F = F_s + F_a + G and a = c_s^2 grad rho + F
-  const T* F = M.F;
-  T a[3] = {M.gr[0] * cs2 + F[0], M.gr[1] * cs2 + F[1], M.gr[2] * cs2 + F[2]};
-  T ugr = u[0] * M.gr[0] + u[1] * M.gr[1] + u[2] * M.gr[2];
-  T uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2];
-  src[0] = ugr;
-  src[1] = -ugr * cs2 + 2 * uF;
-  src[2] = -(7 * ugr * cs2 + 10 * uF);
-  src[3] = F[0];
-  src[4] = -7 * F[0] / 3;
-  src[5] = F[1];
-  src[6] = -7 * F[1] / 3;
-  src[7] = F[2];
-  src[8] = -7 * F[2] / 3;
-  src[9] = 4 * u[0] * a[0] - 2 * u[1] * a[1] - 2 * u[2] * a[2];
-  src[10] = 2 * u[1] * a[1] - 2 * u[2] * a[2];
-  src[11] = u[0] * a[1] + u[1] * a[0];
-  src[12] = u[1] * a[2] + u[2] * a[1];
-  src[13] = u[0] * a[2] + u[2] * a[0];
-  src[14] = 0;
-  T ms[15];
-#pragma unroll
-  for (int r = 0; r < 15; ++r) ms[r] = m[r] - C.lg[r] * (m[r] - eq[r]) + (1 - C.lg[r] / 2) * src[r];
-  // Gamma^-1 = Gamma^T diag(1/15, 1/18, 1/360, 1/10, 1/40, 1/10, 1/40, 1/10, 1/40, 1/12, 1/4, 1/8, 1/8, 1/8, 1/8)
-  T a0 = ms[0] * (T)(1.0 / 15.0), a1 = ms[1] * (T)(1.0 / 18.0), a2 = ms[2] * (T)(1.0 / 360.0);
-  T a3 = ms[3] * (T)(1.0 / 10.0), a4 = ms[4] * (T)(1.0 / 40.0);
-  T a5 = ms[5] * (T)(1.0 / 10.0), a6 = ms[6] * (T)(1.0 / 40.0);
-  T a7 = ms[7] * (T)(1.0 / 10.0), a8 = ms[8] * (T)(1.0 / 40.0);
-  T a9 = ms[9] * (T)(1.0 / 12.0), a10 = ms[10] / 4;
-  T a11 = ms[11] / 8, a12 = ms[12] / 8, a13 = ms[13] / 8, a14 = ms[14] / 8;
-  g[0] = a0 - 2 * a1 + 16 * a2;
-  T F0 = a0 - a1 - 4 * a2;
-  T ex = a3 - 4 * a4, ey = a5 - 4 * a6, ez = a7 - 4 * a8;
-  g[1] = F0 + 2 * a9 + ex;
-  g[2] = F0 + 2 * a9 - ex;
-  g[3] = F0 - a9 + a10 + ey;
-  g[4] = F0 - a9 + a10 - ey;
-  g[5] = F0 - a9 - a10 + ez;
-  g[6] = F0 - a9 - a10 - ez;
-  T base = a0 + a1 + a2, X = a3 + a4, Y = a5 + a6, Z = a7 + a8;
-  // corner c: base + c.(X,Y,Z) + cx cy a11 + cy cz a12 + cx cz a13 + cx cy cz a14
-  T P1 = base + a11 + a12 + a13, Q1 = X + Y + Z + a14;      // (1,1,1)
-  T P2 = base + a11 - a12 - a13, Q2 = X + Y - Z - a14;      // (1,1,-1)
-  T P3 = base - a11 - a12 + a13, Q3 = X - Y + Z - a14;      // (1,-1,1)
-  T P4 = base - a11 + a12 - a13, Q4 = X - Y - Z + a14;      // (1,-1,-1)
-  g[7] = P1 + Q1;
-  g[8] = P1 - Q1;
-  g[9] = P2 + Q2;
-  g[10] = P2 - Q2;
-  g[11] = P3 + Q3;
-  g[12] = P3 - Q3;
-  g[13] = P4 + Q4;
-  g[14] = P4 - Q4;
-}
+using namespace dev;
 
 // ------------------------------------------------------------------ kernels
 constexpr int kBlock = 256;
@@ -363,12 +53,6 @@ __global__ void __launch_bounds__(kBlock) k_mu(Geo G, Coef<typename Prec<P>::T> 
   ((T*)B.mu)[n] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
 }
 
-template <class T>
-__device__ inline bool all_finite(const T* v, int k) {
-  T s = 0;
-  for (int i = 0; i < k; ++i) s += v[i] * (T)0;
-  return s == 0;  // NaN or Inf times 0 is NaN
-}
 
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_step(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {

@@ -14,6 +14,10 @@ hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, 
 // one collide-and-stream step: reads buffer `cur`, writes buffer 1 - cur
 hipError_t launch_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                        hipStream_t s);
+// one step as a single z-marching kernel (fused.hip): reads buffer `cur`,
+// writes buffer 1 - cur
+hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
+                             hipStream_t s);
 // field (MPLB_PHI..MPLB_P) at the current level into B.out (double)
 hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                         int field, hipStream_t s);

@@ -298,9 +298,7 @@ static int check_flag(mplb_t* h) {
 // Enqueue one step of lattice h on stream s.
 static int enqueue_step(mplb_t* h, hipStream_t s) {
   if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
-  HIPCHK(h, launch_phi(h->prec, h->G, h->B, h->cur, s));
-  if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, s));
-  HIPCHK(h, launch_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s));
+  HIPCHK(h, launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s));
   h->cur = 1 - h->cur;
   h->step++;
   return MPLB_OK;
@@ -331,11 +329,9 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
     hipEvent_t* e = &ev[4 * (size_t)k];
     if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
     hipError_t err = hipEventRecord(e[0], h->stream);
-    if (err == hipSuccess) err = launch_phi(h->prec, h->G, h->B, h->cur, h->stream);
     if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
-    if (err == hipSuccess && h->mode == MPLB_COUPLED) err = launch_mu(h->prec, h->G, h->C, h->B, h->stream);
     if (err == hipSuccess) err = hipEventRecord(e[2], h->stream);
-    if (err == hipSuccess) err = launch_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream);
+    if (err == hipSuccess) err = launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream);
     if (err == hipSuccess) err = hipEventRecord(e[3], h->stream);
     if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
     h->cur = 1 - h->cur;
