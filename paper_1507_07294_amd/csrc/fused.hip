@@ -12,11 +12,11 @@
 //       LDS, pulls f and g, forms u, p and the forces (Eqs. 29-30),
 //       d_t(phi u) (Eq. 34), collides both lattices in moment space and
 //       stores f*, g* and (phi u).
-// Each stored population is pulled from HBM by the tile that owns its
-// destination; the halo pulls of (a) and the second pull of the tile's own f
-// in (c) re-read data that blocks running together on one XCD share through
-// its L2 (the block order is remapped so that each XCD gets a contiguous run
-// of tiles).
+// Each stored population is pulled from HBM once, by the tile that owns its
+// destination: the tile's own f, pulled in (a), wait two planes in an LDS
+// queue (thread-private slots) for (c).  Only the halo pulls of (a) re-read
+// data, which blocks running together on one XCD share through its L2 (the
+// block order is remapped so that each XCD gets a contiguous run of tiles).
 //
 // Index arithmetic is hoisted out of the z loop: a thread's x and y source
 // offsets (with periodic wrap) are fixed for the whole march, and the plane
@@ -196,8 +196,10 @@ struct PhiLoader {
     }
   }
 
-  // phi of logical plane zl (mapped onto the lattice) into ring slot s
-  __device__ void load(const Geo& G, const void* fin, int zl, typename Prec<P>::T* s) {
+  // phi of logical plane zl (mapped onto the lattice) into ring slot s; the
+  // own node's pulled f go to q[i * NT + thread] when q is given
+  __device__ void load(const Geo& G, const void* fin, int zl, typename Prec<P>::T* s,
+                       typename Prec<P>::T* q = nullptr) {
     using T = typename Prec<P>::T;
     int mz = map_axis(zl, G.nz, G.wall_z);
     Plane p = make_plane(G, mz);
@@ -205,6 +207,10 @@ struct PhiLoader {
     T f[7];
     pull_col<P, 7, XYWALL, true>(G, fin, own, p, zo + own_xy, f);
     s[own_lds] = phi_of(f);
+    if (q) {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) q[i * R::NT + threadIdx.x] = f[i];
+    }
 #pragma unroll
     for (int k = 0; k < R::HPT; ++k) {
       if (halo_on[k]) {
@@ -269,6 +275,8 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using MU = MuMaker<P, TY>;
   __shared__ T sphi[5][R::NPHI];
   __shared__ T smu[3][MU::NMU];
+  // the own node's pulled f of planes z, z+1, z+2 (thread-private slots)
+  __shared__ T sfq[3][7 * R::NT];
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
@@ -292,13 +300,13 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const int mu_c = (ty + 1) * MU::QX + tx + 1;
 
   // warm-up: phi planes z0-2 .. z0+1, mu planes z0-1, z0
-  for (int zl = z0 - 2; zl <= z0 + 1; ++zl) ld.load(G, fin, zl, sphi[(zl + 10) % 5]);
+  for (int zl = z0 - 2; zl <= z0 + 1; ++zl) ld.load(G, fin, zl, sphi[(zl + 10) % 5], sfq[(zl + 9) % 3]);
   __syncthreads();
   mm.run(G, C, z0 - 1, sphi, smu[(z0 - 1 + 6) % 3]);
   mm.run(G, C, z0, sphi, smu[(z0 + 6) % 3]);
 
   for (int z = z0; z < z1; ++z) {
-    ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5]);
+    ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5], sfq[(z + 2 + 9) % 3]);
     __syncthreads();
     mm.run(G, C, z + 1, sphi, smu[(z + 1 + 6) % 3]);
     __syncthreads();
@@ -306,7 +314,9 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     const int n = z * G.nx * G.ny + col_xy;
     const Plane p = make_plane(G, z);
     T f[7], g[15];
-    pull_col<P, 7, XYWALL, true>(G, fin, col, p, n, f);
+    const T* q = sfq[(z + 9) % 3];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) f[i] = q[i * R::NT + threadIdx.x];
     pull_col<P, 15, XYWALL, false>(G, gin, col, p, n, g);
     T phi = phi_of(f);
     T gphi[3];
@@ -341,6 +351,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 1>;
   __shared__ T sphi[4][R::NPHI];
+  __shared__ T sfq[2][7 * R::NT];  // the own node's pulled f of planes z, z+1
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
@@ -357,15 +368,15 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const int col_xy = gx + G.nx * gy;
   const int lds_c = (ty + 1) * R::PX + tx + 1;
   ld.load(G, fin, z0 - 1, sphi[(z0 - 1 + 8) % 4]);
-  ld.load(G, fin, z0, sphi[(z0 + 8) % 4]);
+  ld.load(G, fin, z0, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
   for (int z = z0; z < z1; ++z) {
-    ld.load(G, fin, z + 1, sphi[(z + 1 + 8) % 4]);
+    ld.load(G, fin, z + 1, sphi[(z + 1 + 8) % 4], sfq[(z + 1) % 2]);
     __syncthreads();
     if (!own) continue;
     const int n = z * G.nx * G.ny + col_xy;
-    const Plane p = make_plane(G, z);
     T f[7];
-    pull_col<P, 7, XYWALL, true>(G, fin, col, p, n, f);
+#pragma unroll
+    for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * R::NT + threadIdx.x];
     T phi = phi_of(f);
     T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c);
     T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
