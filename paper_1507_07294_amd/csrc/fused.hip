@@ -102,20 +102,29 @@ __device__ inline Plane make_plane(const Geo& G, int z) {
 }
 
 // Pull the populations of lattice Q (7 or 15) into node (column c, plane p).
+// The bounce-back choice selects an array and an index and then issues one
+// load, so that no load sits behind a branch and all of them are in flight
+// together; with walls on z only the array choice is uniform over the block.
 template <int P, int Q, bool XYWALL, bool IS_F>
 __device__ inline void pull_col(const Geo& G, const void* base, const Column& c, const Plane& p, int self,
                                 typename Prec<P>::T* v) {
+  using L = Lat<P>;
+  using S = typename L::S;
+  const S* arr = IS_F ? L::fi(base, G.pitch) - G.pitch : (const S*)base;  // arr + i * pitch is population i >= 1
+  if (IS_F) v[0] = (typename Prec<P>::T)L::f0(base)[self];
+  else v[0] = (typename Prec<P>::T)arr[self];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i < Q; ++i) {
     const int cx = Q == 7 ? c7(i, 0) : c15(i, 0), cy = Q == 7 ? c7(i, 1) : c15(i, 1),
               cz = Q == 7 ? c7(i, 2) : c15(i, 2);
     bool b = p.zb[cz + 1];
     if (XYWALL) b = b || c.xb[cx + 1] || c.yb[cy + 1];
-    int src = p.zs[cz + 1] + c.ys[cy + 1] + c.xs[cx + 1];
-    int k = b ? opp(i) : i;
-    int idx = b ? self : src;
-    if (IS_F) v[i] = Lat<P>::ldf(base, G.pitch, k, idx);
-    else v[i] = Lat<P>::ldg(base, G.pitch, k, idx);
+    const int src = p.zs[cz + 1] + c.ys[cy + 1] + c.xs[cx + 1];
+    const S* pa = arr + (size_t)i * G.pitch;
+    const S* pb = arr + (size_t)opp(i) * G.pitch;
+    const S* ptr = b ? pb : pa;
+    const int idx = b ? self : src;
+    v[i] = (typename Prec<P>::T)ptr[idx];
   }
 }
 
