@@ -27,25 +27,61 @@ __host__ __device__ constexpr int c7(int i, int a) {
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 // ---------------------------------------------------------------- storage
-template <int P>
+// Population storage of one time level, in a buffer for f and one for g.
+//   f buffer: f_0 (S0, `pitch` elements), then f_1..f_6;
+//   g buffer: g_0..g_14 (S), each array `pitch` elements.
+// PACK (16-bit populations of the coupled model): f_i and g_i, i = 1..6,
+// share a velocity and therefore a pull source, so they are stored together
+// in one 32-bit word (f_i in the low half, g_i in the high half) in six
+// arrays after f_0; the g buffer then holds g_0 and the corners g_7..g_14.
+template <int P, bool PACK>
 struct Lat {
   using T = typename Prec<P>::T;
   using S0 = typename Prec<P>::S0;
   using S = typename Prec<P>::S;
-  __device__ static const S0* f0(const void* base) { return (const S0*)base; }
-  __device__ static S0* f0(void* base) { return (S0*)base; }
-  __device__ static const S* fi(const void* base, int pitch) { return (const S*)((const char*)base + (size_t)pitch * sizeof(S0)); }
-  __device__ static S* fi(void* base, int pitch) { return (S*)((char*)base + (size_t)pitch * sizeof(S0)); }
-  __device__ static T ldf(const void* base, int pitch, int i, int n) {
-    return i == 0 ? (T)f0(base)[n] : (T)fi(base, pitch)[(size_t)(i - 1) * pitch + n];
+  static_assert(!PACK || sizeof(S) == 2, "packing needs 16-bit populations");
+  __device__ static const S0* f0(const void* fb) { return (const S0*)fb; }
+  __device__ static S0* f0(void* fb) { return (S0*)fb; }
+  // population array i >= 1 of the f buffer (PACK: the 32-bit words as pairs of S)
+  __device__ static const S* fi(const void* fb, int pitch) {
+    return (const S*)((const char*)fb + (size_t)pitch * sizeof(S0));
   }
-  __device__ static void stf(void* base, int pitch, int i, int n, T v) {
-    if (i == 0) f0(base)[n] = (S0)v;
-    else fi(base, pitch)[(size_t)(i - 1) * pitch + n] = (S)v;
+  __device__ static S* fi(void* fb, int pitch) { return (S*)((char*)fb + (size_t)pitch * sizeof(S0)); }
+  __device__ static const uint32_t* words(const void* fb, int pitch) { return (const uint32_t*)fi(fb, pitch); }
+  __device__ static uint32_t* words(void* fb, int pitch) { return (uint32_t*)fi(fb, pitch); }
+  // g array holding population i (PACK: 0 -> 0, 7..14 -> 1..8)
+  __device__ static size_t gslot(int i) { return PACK ? (i == 0 ? 0 : (size_t)(i - 6)) : (size_t)i; }
+
+  __device__ static T ldf(const void* fb, int pitch, int i, int n) {
+    if (i == 0) return (T)f0(fb)[n];
+    size_t k = (size_t)(i - 1) * pitch + n;
+    return PACK ? (T)fi(fb, pitch)[2 * k] : (T)fi(fb, pitch)[k];
   }
-  __device__ static T ldg(const void* base, int pitch, int i, int n) { return (T)((const S*)base)[(size_t)i * pitch + n]; }
-  __device__ static void stg(void* base, int pitch, int i, int n, T v) { ((S*)base)[(size_t)i * pitch + n] = (S)v; }
+  __device__ static void stf(void* fb, int pitch, int i, int n, T v) {
+    if (i == 0) { f0(fb)[n] = (S0)v; return; }
+    size_t k = (size_t)(i - 1) * pitch + n;
+    if (PACK) fi(fb, pitch)[2 * k] = (S)v;
+    else fi(fb, pitch)[k] = (S)v;
+  }
+  __device__ static T ldg(const void* fb, const void* gb, int pitch, int i, int n) {
+    if (PACK && i >= 1 && i <= 6) return (T)fi(fb, pitch)[2 * ((size_t)(i - 1) * pitch + n) + 1];
+    return (T)((const S*)gb)[gslot(i) * pitch + n];
+  }
+  __device__ static void stg(void* fb, void* gb, int pitch, int i, int n, T v) {
+    if (PACK && i >= 1 && i <= 6) fi(fb, pitch)[2 * ((size_t)(i - 1) * pitch + n) + 1] = (S)v;
+    else ((S*)gb)[gslot(i) * pitch + n] = (S)v;
+  }
+  // 16-bit halves <-> compute type
+  __device__ static T lo(uint32_t w) { return (T)__builtin_bit_cast(S, (uint16_t)(w & 0xffffu)); }
+  __device__ static T hi(uint32_t w) { return (T)__builtin_bit_cast(S, (uint16_t)(w >> 16)); }
+  __device__ static uint32_t pack(T a, T b) {
+    return (uint32_t)__builtin_bit_cast(uint16_t, (S)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (S)b) << 16);
+  }
 };
+
+// 16-bit populations of the coupled model are stored packed (see Lat)
+template <int P, bool COUPLED>
+constexpr bool packed() { return COUPLED && sizeof(typename Prec<P>::S) == 2; }
 
 // ---------------------------------------------------------------- geometry
 __device__ inline void decode(const Geo& G, int n, int& x, int& y, int& z) {
@@ -76,21 +112,22 @@ __device__ inline int stencil_nb(const Geo& G, int x, int y, int z, int dx, int 
   return qx + G.nx * (qy + G.ny * qz);
 }
 
-template <int P>
+template <int P, bool PACK>
 __device__ inline void pull_f(const Geo& G, const void* fb, int x, int y, int z, int n, typename Prec<P>::T f[7]) {
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     int s = (i == 0) ? n : pull_src(G, x, y, z, c7(i, 0), c7(i, 1), c7(i, 2));
-    f[i] = (s >= 0) ? Lat<P>::ldf(fb, G.pitch, i, s) : Lat<P>::ldf(fb, G.pitch, opp(i), n);
+    f[i] = (s >= 0) ? Lat<P, PACK>::ldf(fb, G.pitch, i, s) : Lat<P, PACK>::ldf(fb, G.pitch, opp(i), n);
   }
 }
 
-template <int P>
-__device__ inline void pull_g(const Geo& G, const void* gb, int x, int y, int z, int n, typename Prec<P>::T g[15]) {
+template <int P, bool PACK>
+__device__ inline void pull_g(const Geo& G, const void* fb, const void* gb, int x, int y, int z, int n,
+                              typename Prec<P>::T g[15]) {
 #pragma unroll
   for (int i = 0; i < 15; ++i) {
     int s = (i == 0) ? n : pull_src(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2));
-    g[i] = (s >= 0) ? Lat<P>::ldg(gb, G.pitch, i, s) : Lat<P>::ldg(gb, G.pitch, opp(i), n);
+    g[i] = (s >= 0) ? Lat<P, PACK>::ldg(fb, gb, G.pitch, i, s) : Lat<P, PACK>::ldg(fb, gb, G.pitch, opp(i), n);
   }
 }
 

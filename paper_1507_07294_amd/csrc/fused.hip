@@ -25,6 +25,8 @@
 //
 // Finite-difference ghosts: phi beyond a wall is the mirror phi(-1) = phi(0);
 // mu at a ghost position is evaluated at its mirror image, so mu(-1) = mu(0).
+#include <type_traits>
+
 #include "common.h"
 #include "device.h"
 #include "launch.h"
@@ -101,30 +103,57 @@ __device__ inline Plane make_plane(const Geo& G, int z) {
   return p;
 }
 
-// Pull the populations of lattice Q (7 or 15) into node (column c, plane p).
-// The bounce-back choice selects an array and an index and then issues one
-// load, so that no load sits behind a branch and all of them are in flight
-// together; with walls on z only the array choice is uniform over the block.
-template <int P, int Q, bool XYWALL, bool IS_F>
-__device__ inline void pull_col(const Geo& G, const void* base, const Column& c, const Plane& p, int self,
-                                typename Prec<P>::T* v) {
-  using L = Lat<P>;
-  using S = typename L::S;
-  const S* arr = IS_F ? L::fi(base, G.pitch) - G.pitch : (const S*)base;  // arr + i * pitch is population i >= 1
-  if (IS_F) v[0] = (typename Prec<P>::T)L::f0(base)[self];
-  else v[0] = (typename Prec<P>::T)arr[self];
+// Pulls into node (column c, plane p).  The bounce-back choice selects an
+// array and an index and then issues one load, so that no load sits behind a
+// branch and all of them are in flight together; with walls on z only the
+// array choice is uniform over the block.
+template <bool XYWALL>
+__device__ inline bool bounced(const Column& c, const Plane& p, int cx, int cy, int cz) {
+  bool b = p.zb[cz + 1];
+  if (XYWALL) b = b || c.xb[cx + 1] || c.yb[cy + 1];
+  return b;
+}
+__device__ inline int source(const Column& c, const Plane& p, int cx, int cy, int cz) {
+  return p.zs[cz + 1] + c.ys[cy + 1] + c.xs[cx + 1];
+}
+
+// The seven f.  PACK: the words of f_1..f_6 carry g_1..g_6 in their high
+// halves; they are returned raw in w (when w is given).
+template <int P, bool PACK, bool XYWALL>
+__device__ inline void pull_f7(const Geo& G, const void* fb, const Column& c, const Plane& p, int self,
+                               typename Prec<P>::T f[7], uint32_t* w) {
+  using L = Lat<P, PACK>;
+  using T = typename Prec<P>::T;
+  f[0] = (T)L::f0(fb)[self];
 #pragma unroll
-  for (int i = 1; i < Q; ++i) {
-    const int cx = Q == 7 ? c7(i, 0) : c15(i, 0), cy = Q == 7 ? c7(i, 1) : c15(i, 1),
-              cz = Q == 7 ? c7(i, 2) : c15(i, 2);
-    bool b = p.zb[cz + 1];
-    if (XYWALL) b = b || c.xb[cx + 1] || c.yb[cy + 1];
-    const int src = p.zs[cz + 1] + c.ys[cy + 1] + c.xs[cx + 1];
-    const S* pa = arr + (size_t)i * G.pitch;
-    const S* pb = arr + (size_t)opp(i) * G.pitch;
-    const S* ptr = b ? pb : pa;
-    const int idx = b ? self : src;
-    v[i] = (typename Prec<P>::T)ptr[idx];
+  for (int i = 1; i < 7; ++i) {
+    const bool b = bounced<XYWALL>(c, p, c7(i, 0), c7(i, 1), c7(i, 2));
+    const int idx = b ? self : source(c, p, c7(i, 0), c7(i, 1), c7(i, 2));
+    const size_t arr = (size_t)((b ? opp(i) : i) - 1) * G.pitch;
+    if constexpr (PACK) {
+      const uint32_t v = L::words(fb, G.pitch)[arr + idx];
+      f[i] = L::lo(v);
+      if (w) w[i - 1] = v;
+    } else {
+      f[i] = (T)L::fi(fb, G.pitch)[arr + idx];
+    }
+  }
+}
+
+// The fifteen g (PACK: only g_0 and the corners g_7..g_14).
+template <int P, bool PACK, bool XYWALL>
+__device__ inline void pull_g15(const Geo& G, const void* gb, const Column& c, const Plane& p, int self,
+                                typename Prec<P>::T g[15]) {
+  using L = Lat<P, PACK>;
+  using T = typename Prec<P>::T;
+  using S = typename L::S;
+  const S* arr = (const S*)gb;
+  g[0] = (T)arr[self];
+#pragma unroll
+  for (int i = PACK ? 7 : 1; i < 15; ++i) {
+    const bool b = bounced<XYWALL>(c, p, c15(i, 0), c15(i, 1), c15(i, 2));
+    const int idx = b ? self : source(c, p, c15(i, 0), c15(i, 1), c15(i, 2));
+    g[i] = (T)arr[L::gslot(b ? opp(i) : i) * G.pitch + idx];
   }
 }
 
@@ -176,9 +205,12 @@ __device__ inline void halo_pos(int h, int& px, int& py) {
 
 // Per-thread phi-load positions: the own tile node plus up to HPT halo nodes,
 // each as an LDS slot and the source columns of its seven f pulls.
-template <int P, int TY, int HALO, bool XYWALL>
+template <int P, int TY, int HALO, bool XYWALL, bool PACK>
 struct PhiLoader {
   using R = Ring<P, TY, HALO>;
+  using T = typename Prec<P>::T;
+  // queue entry of the own node: the seven f (PACK: f_0's bits and the six raw words)
+  using QT = typename std::conditional<PACK, uint32_t, T>::type;
   Column own;
   int own_lds;
   Column halo[R::HPT];
@@ -206,24 +238,29 @@ struct PhiLoader {
   }
 
   // phi of logical plane zl (mapped onto the lattice) into ring slot s; the
-  // own node's pulled f go to q[i * NT + thread] when q is given
-  __device__ void load(const Geo& G, const void* fin, int zl, typename Prec<P>::T* s,
-                       typename Prec<P>::T* q = nullptr) {
-    using T = typename Prec<P>::T;
+  // own node's pulled populations go to q[i * NT + thread] when q is given
+  __device__ void load(const Geo& G, const void* fin, int zl, T* s, QT* q = nullptr) {
     int mz = map_axis(zl, G.nz, G.wall_z);
     Plane p = make_plane(G, mz);
     int zo = mz * G.nx * G.ny;
     T f[7];
-    pull_col<P, 7, XYWALL, true>(G, fin, own, p, zo + own_xy, f);
+    uint32_t w[6];
+    pull_f7<P, PACK, XYWALL>(G, fin, own, p, zo + own_xy, f, w);
     s[own_lds] = phi_of(f);
     if (q) {
+      if constexpr (PACK) {
+        q[threadIdx.x] = __builtin_bit_cast(uint32_t, (float)f[0]);
 #pragma unroll
-      for (int i = 0; i < 7; ++i) q[i * R::NT + threadIdx.x] = f[i];
+        for (int i = 1; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)w[i - 1];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)f[i];
+      }
     }
 #pragma unroll
     for (int k = 0; k < R::HPT; ++k) {
       if (halo_on[k]) {
-        pull_col<P, 7, XYWALL, true>(G, fin, halo[k], p, zo + halo_xy[k], f);
+        pull_f7<P, PACK, XYWALL>(G, fin, halo[k], p, zo + halo_xy[k], f, nullptr);
         s[halo_lds[k]] = phi_of(f);
       }
     }
@@ -282,10 +319,14 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 2>;
   using MU = MuMaker<P, TY>;
+  constexpr bool PACK = packed<P, true>();
+  using L = Lat<P, PACK>;
+  using LD = PhiLoader<P, TY, 2, XYWALL, PACK>;
+  using QT = typename LD::QT;
   __shared__ T sphi[5][R::NPHI];
   __shared__ T smu[3][MU::NMU];
-  // the own node's pulled f of planes z, z+1, z+2 (thread-private slots)
-  __shared__ T sfq[3][7 * R::NT];
+  // the own node's pulled populations of planes z, z+1, z+2 (thread-private slots)
+  __shared__ QT sfq[3][7 * R::NT];
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
@@ -299,7 +340,7 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   void* go = B.g[1 - cur];
   T* hist = (T*)B.phiu;
 
-  PhiLoader<P, TY, 2, XYWALL> ld;
+  LD ld;
   ld.init(G, x0, y0);
   MU mm;
   mm.init(G, x0, y0);
@@ -323,10 +364,20 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     const int n = z * G.nx * G.ny + col_xy;
     const Plane p = make_plane(G, z);
     T f[7], g[15];
-    const T* q = sfq[(z + 9) % 3];
+    const QT* q = sfq[(z + 9) % 3];
+    if constexpr (PACK) {
+      f[0] = (T)__builtin_bit_cast(float, (uint32_t)q[threadIdx.x]);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) f[i] = q[i * R::NT + threadIdx.x];
-    pull_col<P, 15, XYWALL, false>(G, gin, col, p, n, g);
+      for (int i = 1; i < 7; ++i) {
+        const uint32_t w = (uint32_t)q[i * R::NT + threadIdx.x];
+        f[i] = L::lo(w);
+        g[i] = L::hi(w);
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) f[i] = (T)q[i * R::NT + threadIdx.x];
+    }
+    pull_g15<P, PACK, XYWALL>(G, gin, col, p, n, g);
     T phi = phi_of(f);
     T gphi[3];
     grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi);
@@ -344,10 +395,20 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
     collide_ns(C, g, M);
+    if constexpr (PACK) {
+      L::f0(fo)[n] = (typename L::S0)f[0];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
+      for (int i = 1; i < 7; ++i) L::words(fo, G.pitch)[(size_t)(i - 1) * G.pitch + n] = L::pack(f[i], g[i]);
+      typename L::S* ga = (typename L::S*)go;
+      ga[n] = (typename L::S)g[0];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) Lat<P>::stg(go, G.pitch, i, n, g[i]);
+      for (int i = 7; i < 15; ++i) ga[L::gslot(i) * G.pitch + n] = (typename L::S)g[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 7; ++i) L::stf(fo, G.pitch, i, n, f[i]);
+#pragma unroll
+      for (int i = 0; i < 15; ++i) L::stg(fo, go, G.pitch, i, n, g[i]);
+    }
     if (!(all_finite(f, 7) && all_finite(g, 15))) *B.flag = 1;
   }
 }
@@ -359,6 +420,7 @@ __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(wa
 k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 1>;
+  using L = Lat<P, false>;
   __shared__ T sphi[4][R::NPHI];
   __shared__ T sfq[2][7 * R::NT];  // the own node's pulled f of planes z, z+1
   const int lb = logical_block(blockIdx.x, gridDim.x);
@@ -371,7 +433,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const void* fin = B.f[cur];
   void* fo = B.f[1 - cur];
   T* hist = (T*)B.phiu;
-  PhiLoader<P, TY, 1, XYWALL> ld;
+  PhiLoader<P, TY, 1, XYWALL, false> ld;
   ld.init(G, x0, y0);
   const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
   const int col_xy = gx + G.nx * gy;
@@ -400,7 +462,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     }
     collide_che(C, f, phi, mu, u, dphiu);
 #pragma unroll
-    for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
+    for (int i = 0; i < 7; ++i) L::stf(fo, G.pitch, i, n, f[i]);
     if (!all_finite(f, 7)) *B.flag = 1;
   }
 }

@@ -7,13 +7,13 @@
 // wall (half-way bounce-back).  Arrays are structure-of-arrays, one array per
 // population, `pitch` elements apart.
 //
-// One coupled step = three kernels:
-//   k_phi   phi = sum_i f_i (Eq. 13)
-//   k_mu    mu = 4 beta phi (phi^2 - 1) - k lap phi (Eqs. 2, 36)
-//   k_step  grad phi, lap mu (Eqs. 35-36); u, p (Eqs. 29-30); forces (after
-//           Eq. 28); d_t(phi u) (Eq. 34); D3Q7 and D3Q15 collisions in moment
-//           space (Eqs. 15, 17-18, 20, 31-32) with the sparse structure of M
-//           and Gamma written out; stores into buffer 1 - cur.
+// The time step itself is one kernel (fused.hip).  This file holds the
+// per-node kernels around it:
+//   k_phi, k_mu   phi = sum_i f_i (Eq. 13) and mu (Eqs. 2, 36) into arrays,
+//                 for read-out, totals and the initial state
+//   k_macro       one macroscopic field at the current level
+//   k_totals      FP64 sums of phi, momentum and force, non-finite count
+//   k_init        equilibrium initial state (Eqs. 5, 21)
 #include <cmath>
 
 #include "common.h"
@@ -28,7 +28,7 @@ using namespace dev;
 // ------------------------------------------------------------------ kernels
 constexpr int kBlock = 256;
 
-template <int P>
+template <int P, bool COUPLED>
 __global__ void __launch_bounds__(kBlock) k_phi(Geo G, Bufs B, int cur) {
   using T = typename Prec<P>::T;
   int n = blockIdx.x * kBlock + threadIdx.x;
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kBlock) k_phi(Geo G, Bufs B, int cur) {
   int x, y, z;
   decode(G, n, x, y, z);
   T f[7];
-  pull_f<P>(G, B.f[cur], x, y, z, n, f);
+  pull_f<P, packed<P, COUPLED>()>(G, B.f[cur], x, y, z, n, f);
   ((T*)B.phi)[n] = phi_of(f);
 }
 
@@ -54,73 +54,6 @@ __global__ void __launch_bounds__(kBlock) k_mu(Geo G, Coef<typename Prec<P>::T> 
 }
 
 
-template <int P>
-__global__ void __launch_bounds__(kBlock) k_step(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {
-  using T = typename Prec<P>::T;
-  int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= G.N) return;
-  int x, y, z;
-  decode(G, n, x, y, z);
-  T f[7], g[15];
-  pull_f<P>(G, B.f[cur], x, y, z, n, f);
-  pull_g<P>(G, B.g[cur], x, y, z, n, g);
-  T phi = phi_of(f);
-  const T* phis = (const T*)B.phi;
-  const T* mus = (const T*)B.mu;
-  T mu = mus[n], gphi[3], lapphi, gdummy[3], lapmu;
-  grad_lap(G, phis, x, y, z, phi, gphi, lapphi, true);
-  grad_lap(G, mus, x, y, z, mu, gdummy, lapmu, false);
-  Macro<T> M;
-  flow_macro(C, g, phi, mu, gphi, lapmu, M);
-  T* hist = (T*)B.phiu;
-  T dphiu[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T pu = phi * M.u[a];
-    dphiu[a] = pu - hist[(size_t)a * G.pitch + n];
-    hist[(size_t)a * G.pitch + n] = pu;
-  }
-  collide_che(C, f, phi, mu, M.u, dphiu);
-  collide_ns(C, g, M);
-  void* fo = B.f[1 - cur];
-  void* go = B.g[1 - cur];
-#pragma unroll
-  for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
-#pragma unroll
-  for (int i = 0; i < 15; ++i) Lat<P>::stg(go, G.pitch, i, n, g[i]);
-  if (!(all_finite(f, 7) && all_finite(g, 15))) *B.flag = 1;
-}
-
-template <int P>
-__global__ void __launch_bounds__(kBlock) k_step_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {
-  using T = typename Prec<P>::T;
-  int n = blockIdx.x * kBlock + threadIdx.x;
-  if (n >= G.N) return;
-  int x, y, z;
-  decode(G, n, x, y, z);
-  T f[7];
-  pull_f<P>(G, B.f[cur], x, y, z, n, f);
-  T phi = phi_of(f);
-  T gr[3], lap;
-  grad_lap(G, (const T*)B.phi, x, y, z, phi, gr, lap, false);
-  T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
-  T u[3];
-  presc_u(G, C, (const T*)B.ufield, x, y, z, n, u);
-  T* hist = (T*)B.phiu;
-  T dphiu[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    T pu = phi * u[a];
-    dphiu[a] = pu - hist[(size_t)a * G.pitch + n];
-    hist[(size_t)a * G.pitch + n] = pu;
-  }
-  collide_che(C, f, phi, mu, u, dphiu);
-  void* fo = B.f[1 - cur];
-#pragma unroll
-  for (int i = 0; i < 7; ++i) Lat<P>::stf(fo, G.pitch, i, n, f[i]);
-  if (!all_finite(f, 7)) *B.flag = 1;
-}
-
 // Macroscopic state of node n at the current level (phi and mu arrays must
 // hold this level).  Returns false if a pulled population is non-finite.
 template <int P, bool COUPLED>
@@ -129,13 +62,14 @@ __device__ inline bool node_macro(const Geo& G, const Coef<typename Prec<P>::T>&
   using T = typename Prec<P>::T;
   int x, y, z;
   decode(G, n, x, y, z);
+  constexpr bool PK = packed<P, COUPLED>();
   T f[7];
-  pull_f<P>(G, B.f[cur], x, y, z, n, f);
+  pull_f<P, PK>(G, B.f[cur], x, y, z, n, f);
   T phi = phi_of(f);
   bool ok = all_finite(f, 7);
   if (COUPLED) {
     T g[15];
-    pull_g<P>(G, B.g[cur], x, y, z, n, g);
+    pull_g<P, PK>(G, B.f[cur], B.g[cur], x, y, z, n, g);
     ok = ok && all_finite(g, 15);
     const T* mus = (const T*)B.mu;
     T mu = mus[n], gphi[3], lapphi, gd[3], lapmu;
@@ -196,7 +130,7 @@ __global__ void __launch_bounds__(kBlock) k_totals(Geo G, Coef<typename Prec<P>:
       int x, y, z;
       decode(G, n, x, y, z);
       T g[15];
-      pull_g<P>(G, B.g[cur], x, y, z, n, g);
+      pull_g<P, packed<P, COUPLED>()>(G, B.f[cur], B.g[cur], x, y, z, n, g);
       double gd[15];
       for (int i = 0; i < 15; ++i) gd[i] = (double)g[i];
       for (int i = 0; i < 15; ++i) {
@@ -279,8 +213,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     int s = (i == 0) ? n : pull_src(G, x, y, z, c7(i, 0), c7(i, 1), c7(i, 2));
-    if (s >= 0) Lat<P>::stf(B.f[cur], G.pitch, i, s, feq[i]);
-    else Lat<P>::stf(B.f[cur], G.pitch, opp(i), n, feq[i]);
+    if (s >= 0) Lat<P, packed<P, COUPLED>()>::stf(B.f[cur], G.pitch, i, s, feq[i]);
+    else Lat<P, packed<P, COUPLED>()>::stf(B.f[cur], G.pitch, opp(i), n, feq[i]);
   }
   if (COUPLED) {
     T rho = (1 + phi) / 2 * C.rho_l + (1 - phi) / 2 * C.rho_g;
@@ -291,8 +225,8 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T
       T cu = c15(i, 0) * u[0] + c15(i, 1) * u[1] + c15(i, 2) * u[2];
       T geq = rho * w * (3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);  // Eq. 21 with p = 0
       int s = (i == 0) ? n : pull_src(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2));
-      if (s >= 0) Lat<P>::stg(B.g[cur], G.pitch, i, s, geq);
-      else Lat<P>::stg(B.g[cur], G.pitch, opp(i), n, geq);
+      if (s >= 0) Lat<P, packed<P, COUPLED>()>::stg(B.f[cur], B.g[cur], G.pitch, i, s, geq);
+      else Lat<P, packed<P, COUPLED>()>::stg(B.f[cur], B.g[cur], G.pitch, opp(i), n, geq);
     }
   }
   for (int a = 0; a < 3; ++a) hist[(size_t)a * G.pitch + n] = phi * u[a];
@@ -309,11 +243,12 @@ __global__ void k_fill_zero(T* p, int count) {
   if (i < count) p[i] = (T)0;
 }
 
-template <int P>
+template <int P, bool COUPLED>
 __global__ void k_poke(Geo G, Bufs B, int cur, int set, int i, int n, double v) {
   using T = typename Prec<P>::T;
-  if (set == 0) Lat<P>::stf(B.f[cur], G.pitch, i, n, (T)v);
-  else Lat<P>::stg(B.g[cur], G.pitch, i, n, (T)v);
+  using L = Lat<P, packed<P, COUPLED>()>;
+  if (set == 0) L::stf(B.f[cur], G.pitch, i, n, (T)v);
+  else L::stg(B.f[cur], B.g[cur], G.pitch, i, n, (T)v);
 }
 
 template <class T>
@@ -330,15 +265,6 @@ Coef<T> cast_coef(const Coef<double>& c) {
 }
 
 inline dim3 grid_for(int N) { return dim3((unsigned)((N + kBlock - 1) / kBlock)); }
-
-template <int P>
-hipError_t step_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur, hipStream_t s) {
-  using T = typename Prec<P>::T;
-  Coef<T> C = cast_coef<T>(Cd);
-  if (mode == MPLB_COUPLED) hipLaunchKernelGGL(k_step<P>, grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur);
-  else hipLaunchKernelGGL(k_step_che<P>, grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur);
-  return hipGetLastError();
-}
 
 template <int P>
 hipError_t macro_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur, int field, hipStream_t s) {
@@ -383,9 +309,10 @@ hipError_t init_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs&
     default: return hipErrorInvalidValue;           \
   }
 
-hipError_t launch_phi(int P, const Geo& G, const Bufs& B, int cur, hipStream_t s) {
+hipError_t launch_phi(int P, int mode, const Geo& G, const Bufs& B, int cur, hipStream_t s) {
   MPLB_DISPATCH(P, {
-    hipLaunchKernelGGL(k_phi<PP>, grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
+    if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_phi<PP, true>), grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
+    else hipLaunchKernelGGL((k_phi<PP, false>), grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
     return hipGetLastError();
   })
 }
@@ -396,10 +323,6 @@ hipError_t launch_mu(int P, const Geo& G, const Coef<double>& Cd, const Bufs& B,
     hipLaunchKernelGGL(k_mu<PP>, grid_for(G.N), dim3(kBlock), 0, s, G, cast_coef<T>(Cd), B);
     return hipGetLastError();
   })
-}
-
-hipError_t launch_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur, hipStream_t s) {
-  MPLB_DISPATCH(P, return step_impl<PP>(mode, G, C, B, cur, s))
 }
 
 hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur, int field,
@@ -432,9 +355,11 @@ hipError_t launch_fill_zero(int P, void* p, int count, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_poke(int P, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v, hipStream_t s) {
+hipError_t launch_poke(int P, int mode, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v,
+                       hipStream_t s) {
   MPLB_DISPATCH(P, {
-    hipLaunchKernelGGL(k_poke<PP>, dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
+    if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_poke<PP, true>), dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
+    else hipLaunchKernelGGL((k_poke<PP, false>), dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
     return hipGetLastError();
   })
 }

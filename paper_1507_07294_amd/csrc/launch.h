@@ -8,12 +8,9 @@
 namespace mplb {
 
 // phi = sum_i f_i over the pulled populations of buffer `cur` (Eq. 13)
-hipError_t launch_phi(int P, const Geo& G, const Bufs& B, int cur, hipStream_t s);
+hipError_t launch_phi(int P, int mode, const Geo& G, const Bufs& B, int cur, hipStream_t s);
 // mu from phi (Eqs. 2, 36)
 hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, hipStream_t s);
-// one collide-and-stream step: reads buffer `cur`, writes buffer 1 - cur
-hipError_t launch_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
-                       hipStream_t s);
 // one step as a single z-marching kernel (fused.hip): reads buffer `cur`,
 // writes buffer 1 - cur
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
@@ -32,7 +29,7 @@ hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, con
 hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
 hipError_t launch_fill_zero(int P, void* p, int count, hipStream_t s);
 // overwrite stored population i (set 0: f, 1: g) at storage index n of buffer cur
-hipError_t launch_poke(int P, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v,
+hipError_t launch_poke(int P, int mode, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v,
                        hipStream_t s);
 
 }  // namespace mplb

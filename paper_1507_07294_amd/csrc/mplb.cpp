@@ -37,8 +37,11 @@ Plan make_plan(long long N, int prec, int mode) {
   p.pitch = align_up((size_t)N, 256) + kPitchPad;
   const size_t A = 256;
   size_t sT = comp_size(prec), s0 = store0_size(prec), sS = store_size(prec);
-  p.f = align_up(p.pitch * s0 + 6 * p.pitch * sS, A);
-  p.g = mode == MPLB_COUPLED ? align_up(15 * p.pitch * sS, A) : 0;
+  // 16-bit populations of the coupled model: f_i and g_i (i = 1..6) share
+  // 32-bit words in the f buffer; the g buffer keeps g_0 and the 8 corners
+  bool pack = mode == MPLB_COUPLED && sS == 2;
+  p.f = align_up(p.pitch * s0 + 6 * p.pitch * (pack ? 4 : sS), A);
+  p.g = mode == MPLB_COUPLED ? align_up((pack ? 9 : 15) * p.pitch * sS, A) : 0;
   p.phiu = align_up(3 * p.pitch * sT, A);
   p.phi = align_up(p.pitch * sT, A);
   p.mu = align_up(p.pitch * sT, A);
@@ -377,7 +380,7 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
 }
 
 static int prepare_macro(mplb_t* h) {
-  HIPCHK(h, launch_phi(h->prec, h->G, h->B, h->cur, h->stream));
+  HIPCHK(h, launch_phi(h->prec, h->mode, h->G, h->B, h->cur, h->stream));
   if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
   if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
   return MPLB_OK;
@@ -458,7 +461,7 @@ int mplb_poke(mplb_t* h, int set, int i, long node, double value) {
   if (!h || set < 0 || set > 1 || i < 0 || node < 0 || node >= h->G.N) return MPLB_E_INVAL;
   if ((set == 0 && i > 6) || (set == 1 && (i > 14 || h->mode != MPLB_COUPLED))) return MPLB_E_INVAL;
   if (!h->have_init) return fail(h, MPLB_E_STATE, "poke before init");
-  HIPCHK(h, launch_poke(h->prec, h->G, h->B, h->cur, set, i, (int)node, value, h->stream));
+  HIPCHK(h, launch_poke(h->prec, h->mode, h->G, h->B, h->cur, set, i, (int)node, value, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return MPLB_OK;
 }
