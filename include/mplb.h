@@ -160,6 +160,12 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes);
  * Synchronises; the state advances exactly as with mplb_step. */
 int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
 
+/* Measurement reference: copy `bytes` (a multiple of 16) from device buffer
+ * src to device buffer dst with 16-byte loads and stores on hip_stream, so
+ * that the bandwidth a plain streaming kernel reaches on this device can be
+ * put beside the step's.  Enqueues only. */
+int mplb_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;
  * node n) of the current state with `value`, e.g. to plant a NaN. */
 int mplb_poke(mplb_t* h, int set, int i, long node, double value);

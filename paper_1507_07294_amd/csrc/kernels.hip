@@ -232,6 +232,11 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T
   for (int a = 0; a < 3; ++a) hist[(size_t)a * G.pitch + n] = phi * u[a];
 }
 
+// plain streaming copy with 16-byte accesses (bandwidth reference)
+__global__ void __launch_bounds__(kBlock) k_copy16(const float4* __restrict__ a, float4* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) b[i] = a[i];
+}
+
 __global__ void k_fill_int(int* p, int v, int count) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = v;
@@ -342,6 +347,11 @@ hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStrea
 
 hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur, hipStream_t s) {
   MPLB_DISPATCH(P, return init_impl<PP>(mode, G, C, B, cur, s))
+}
+
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy16, dim3(32768), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst, bytes / 16);
+  return hipGetLastError();
 }
 
 hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s) {

@@ -457,6 +457,11 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
   return MPLB_OK;
 }
 
+int mplb_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream) {
+  if (!src || !dst || bytes % 16) return MPLB_E_INVAL;
+  return launch_copy_probe(src, dst, bytes, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK : MPLB_E_DEVICE;
+}
+
 int mplb_poke(mplb_t* h, int set, int i, long node, double value) {
   if (!h || set < 0 || set > 1 || i < 0 || node < 0 || node >= h->G.N) return MPLB_E_INVAL;
   if ((set == 0 && i > 6) || (set == 1 && (i > 14 || h->mode != MPLB_COUPLED))) return MPLB_E_INVAL;

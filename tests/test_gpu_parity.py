@@ -7,6 +7,8 @@ helpers.FLOORS (1e-6 for phi, rho, u; 1e-5 for p; 1e-8 for mu; lattice units):
   nearly equal terms away from the interface).
   FP16 / BF16 population storage: 5e-3 / 5e-2 on every field.
 The measured errors are printed for every case."""
+import functools
+
 import numpy as np
 import pytest
 
@@ -162,3 +164,54 @@ def test_storage_precision_error(precision):
     w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 81, coupled=True)
     tol = 5e-3 if precision == "f16" else 5e-2
     _compare(w, [1, 10, 100, 200], precision, tol)
+
+
+@functools.lru_cache(maxsize=1)
+def _full_size_case(W=256):
+    """The benchmark's Rayleigh-Taylor box (W x W x 4W, Re = 4000) with a seeded
+    smooth perturbation of phi and a seeded initial velocity, so that every
+    term of the step is exercised from the first step."""
+    w = wl.rayleigh_taylor(W=W, Re=4000.0)
+    rng = np.random.default_rng(4242)
+    w.phi0 = np.clip(w.phi0 + wl.smooth_field(w.shape, rng, 0.02, modes=2), -1.0, 1.0)
+    w.u0 = wl.smooth_field(w.shape, rng, 0.01, modes=2, components=3)
+    w.u0[2][0] = 0.0
+    w.u0[2][-1] = 0.0
+    return w
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3)])
+def test_full_size_sampled(precision, tol):
+    """256 x 256 x 1024 in the launch configuration the benchmark times: the
+    GPU fields after 2 steps equal the FP64 oracle, evaluated on a window around
+    each sampled node, at tile edges (x = 63/64, y = 7/8), z-segment edges and
+    both walls.  Error per field: max |gpu - oracle| over the samples divided by
+    the field's largest magnitude there."""
+    w = _full_size_case()
+    nx, ny, nz = w.shape
+    print(f"\n[case] full-size {w.shape} {precision}", flush=True)
+    g = helpers.gpu_for(w, precision)
+    steps = 2
+    g.step(steps)
+    fields = ("phi", "mu", "ux", "uy", "uz", "p")
+    got = {k: g.read(k) for k in fields}
+    g.destroy()
+    rng = np.random.default_rng(7)
+    nodes = [(0, 0, 0), (63, 7, 1), (64, 8, 63), (255, 255, nz - 1), (127, 128, 64), (191, 200, nz // 2),
+             (5, 250, nz // 2 + 1), (250, 3, nz - 2), (64, 7, 128), (63, 8, 127)]
+    nodes += [tuple(int(v) for v in rng.integers(0, (nx, ny, nz))) for _ in range(10)]
+    ref = {k: [] for k in fields}
+    val = {k: [] for k in fields}
+    for (x, y, z) in nodes:
+        o = helpers.window_oracle_fields(w, (x, y, z), steps)
+        for k in fields:
+            ref[k].append(o[k])
+            val[k].append(got[k][z, y, x])
+    errs = {}
+    for k in fields:
+        r, v = np.array(ref[k]), np.array(val[k])
+        scale = max(np.abs(r).max(), helpers.FLOORS[k])
+        errs[k] = np.abs(v - r).max() / scale
+        print(f"  {k}: max err {errs[k]:.2e} (scale {scale:.2e})", flush=True)
+    for k, e in errs.items():
+        assert e <= (tol[k] if isinstance(tol, dict) else tol), (k, e)
