@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--no-che", action="store_true", help="skip the CHE-only interface-tracking line")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
+    ap.add_argument("--serving-requests", type=int, default=48,
+                    help="requests in the serving trace (0: skip the serving leg)")
+    ap.add_argument("--serving-steps", type=int, default=400)
     return ap.parse_args()
 
 
@@ -202,6 +205,23 @@ def main():
         result["copy_probe_GBps"] = probe
         del a, b
         torch.cuda.empty_cache()
+
+    if args.serving_requests > 0:
+        from paper_1507_07294_amd import serve
+        print(f"[bench] serving {args.serving_requests} requests x {args.serving_steps} steps",
+              file=sys.stderr, flush=True)
+        trace = wl.serving_trace(n_requests=args.serving_requests, steps=args.serving_steps, mean_gap_s=0.003)
+        srv = serve.Server("f32", 16e9, chunk=50)
+        _, mix = srv.run(trace)
+        _, b2b = serve.run_back_to_back(trace, "f32", chunk=50)
+        result["serving"] = {
+            "trace": f"{args.serving_requests} requests, Poisson arrivals (mean gap 3 ms, seed 20261202), half "
+                     f"droplets (32^3..128^3) half Rayleigh-Taylor (W = 32..64), {args.serving_steps} steps each, "
+                     "FP32, HBM budget 16 GB",
+            "batched": {k: round(v, 4) for k, v in mix.items()},
+            "back_to_back": {k: round(v, 4) for k, v in b2b.items()},
+            "mean_batch": round(float(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes))), 2),
+            "peak_bytes": srv.peak_bytes}
 
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -56,6 +56,23 @@ struct Bufs {
 
 constexpr int kRedSlots = 2048;
 
+// Work split of the z-marching step: tiles of 64 x TY columns, z segments
+// of lz planes.
+struct Tiling {
+  int tiles_x, tiles_y, lz, nseg;
+};
+
+// One lattice of a batched step: its geometry, coefficients, buffers, work
+// split, buffer parity and first block in the batch grid.
+template <class T>
+struct BatchItem {
+  Geo G;
+  Tiling TL;
+  Bufs B;
+  Coef<T> C;
+  int cur0, block0, nblocks, pad;
+};
+
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace mplb

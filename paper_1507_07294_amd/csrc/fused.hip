@@ -56,10 +56,6 @@ __device__ inline int map_axis(int v, int n, int wall) {
 __device__ inline int clamp_axis(int v, int n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
 __device__ inline int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
 
-struct Tiling {
-  int tiles_x, tiles_y, lz, nseg;
-};
-
 // Source offsets of one lattice column (x, y): for a velocity component c in
 // {-1, 0, 1}, xs[c+1] is the source x (x - c, wrapped) and xb[c+1] says the
 // population comes through an x wall; ys holds y * nx likewise.
@@ -313,9 +309,10 @@ struct MuMaker {
 template <int P>
 constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
 
+// The coupled step of logical block lb of one lattice.
 template <int P, int TY, bool XYWALL>
-__global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
-k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+__device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
+                                  const Tiling& TL, int lb) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 2>;
   using MU = MuMaker<P, TY>;
@@ -327,7 +324,6 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   __shared__ T smu[3][MU::NMU];
   // the own node's pulled populations of planes z, z+1, z+2 (thread-private slots)
   __shared__ QT sfq[3][7 * R::NT];
-  const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
   const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
@@ -411,6 +407,31 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     }
     if (!(all_finite(f, 7) && all_finite(g, 15))) *B.flag = 1;
   }
+}
+
+template <int P, int TY, bool XYWALL>
+__global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
+k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+  fused_body<P, TY, XYWALL>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
+}
+
+// Many lattices in one launch (continuous batching): the blocks of all
+// lattices form one grid; a block finds its lattice in the device table by
+// its (XCD-remapped) index and runs the same body as k_fused, so each
+// lattice computes exactly what it computes alone.  Buffer parity of item i
+// is cur0 ^ flip.
+template <int P, int TY, bool XYWALL>
+__global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
+k_fused_many(const BatchItem<typename Prec<P>::T>* tab, int count, int flip) {
+  const int b = logical_block(blockIdx.x, gridDim.x);
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) / 2;
+    if (tab[mid].block0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const BatchItem<typename Prec<P>::T> it = tab[lo];
+  fused_body<P, TY, XYWALL>(it.G, it.C, it.B, it.cur0 ^ flip, it.TL, b - it.block0);
 }
 
 // CHE-only: mu is needed at the node only, so phi needs a halo of one and a
@@ -521,6 +542,29 @@ hipError_t fused_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs
   return fused_impl2<P, false>(mode, G, C, B, cur, s);
 }
 
+template <int P, bool XYWALL>
+hipError_t many_impl2(const void* dtab, int count, int total_blocks, int flip, hipStream_t s) {
+  using T = typename Prec<P>::T;
+  hipLaunchKernelGGL((k_fused_many<P, kTY, XYWALL>), dim3((unsigned)total_blocks), dim3(kTX * kTY), 0, s,
+                     (const BatchItem<T>*)dtab, count, flip);
+  return hipGetLastError();
+}
+
+template <int P>
+int batch_fill_impl(void* table, int i, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur0, int block0) {
+  using T = typename Prec<P>::T;
+  BatchItem<T> it{};
+  it.G = G;
+  it.TL = make_tiling(G, kTY, 16);
+  it.B = B;
+  it.C = cast_coef_f<T>(Cd);
+  it.cur0 = cur0;
+  it.block0 = block0;
+  it.nblocks = it.TL.tiles_x * it.TL.tiles_y * it.TL.nseg;
+  ((BatchItem<T>*)table)[i] = it;
+  return it.nblocks;
+}
+
 }  // namespace
 
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
@@ -532,6 +576,36 @@ hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& 
     case MPLB_F32_BF16: return fused_impl<MPLB_F32_BF16>(mode, G, C, B, cur, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+size_t fused_batch_item_bytes(int P) {
+  return P == MPLB_F64 ? sizeof(BatchItem<double>) : sizeof(BatchItem<float>);
+}
+
+int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>& C, const Bufs& B, int cur0,
+                     int block0) {
+  switch (P) {
+    case MPLB_F64: return batch_fill_impl<MPLB_F64>(table, i, G, C, B, cur0, block0);
+    case MPLB_F32: return batch_fill_impl<MPLB_F32>(table, i, G, C, B, cur0, block0);
+    case MPLB_F32_F16: return batch_fill_impl<MPLB_F32_F16>(table, i, G, C, B, cur0, block0);
+    case MPLB_F32_BF16: return batch_fill_impl<MPLB_F32_BF16>(table, i, G, C, B, cur0, block0);
+    default: return -1;
+  }
+}
+
+hipError_t launch_fused_many(int P, bool xywall, const void* dtab, int count, int total_blocks, int flip,
+                             hipStream_t s) {
+#define MPLB_MANY(PP)                                                        \
+  return xywall ? many_impl2<PP, true>(dtab, count, total_blocks, flip, s) \
+                : many_impl2<PP, false>(dtab, count, total_blocks, flip, s);
+  switch (P) {
+    case MPLB_F64: MPLB_MANY(MPLB_F64)
+    case MPLB_F32: MPLB_MANY(MPLB_F32)
+    case MPLB_F32_F16: MPLB_MANY(MPLB_F32_F16)
+    case MPLB_F32_BF16: MPLB_MANY(MPLB_F32_BF16)
+    default: return hipErrorInvalidValue;
+  }
+#undef MPLB_MANY
 }
 
 }  // namespace mplb

@@ -15,6 +15,15 @@ hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, 
 // writes buffer 1 - cur
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                              hipStream_t s);
+// Batched coupled step over a device table of BatchItem<T> (T of P):
+// fused_batch_item_bytes gives the item size, fused_batch_fill writes item i
+// of a host table and returns that lattice's block count, launch_fused_many
+// runs one step of every item (buffer parity cur0 ^ flip).
+size_t fused_batch_item_bytes(int P);
+int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>& C, const Bufs& B, int cur0,
+                     int block0);
+hipError_t launch_fused_many(int P, bool xywall, const void* dtab, int count, int total_blocks, int flip,
+                             hipStream_t s);
 // field (MPLB_PHI..MPLB_P) at the current level into B.out (double)
 hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                         int field, hipStream_t s);

@@ -363,17 +363,85 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
   return rc;
 }
 
+// Device table of a batched step and its pinned host staging (grow-only,
+// one per device; batched calls on one device are not thread-safe).
+struct BatchTable {
+  void* dev = nullptr;
+  size_t dev_cap = 0;
+  void* host = nullptr;
+  size_t host_cap = 0;
+  hipEvent_t uploaded = nullptr;
+};
+static BatchTable g_tables[64];
+
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   if (!hs || count < 0 || nsteps < 0) return MPLB_E_INVAL;
-  if (count == 0) return MPLB_OK;
+  if (count == 0 || nsteps == 0) return MPLB_OK;
   for (int i = 0; i < count; ++i) {
     if (!hs[i]) return MPLB_E_INVAL;
     if (!hs[i]->have_init) return fail(hs[i], MPLB_E_STATE, "step before init");
+    if (hs[i]->prec != hs[0]->prec || hs[i]->mode != hs[0]->mode)
+      return fail(hs[0], MPLB_E_INVAL, "step_many needs one precision and one mode");
+    for (int j = 0; j < i; ++j)
+      if (hs[j] == hs[i]) return fail(hs[0], MPLB_E_INVAL, "a lattice appears twice in step_many");
   }
-  hipStream_t s = hs[0]->stream;
-  for (int k = 0; k < nsteps; ++k)
+  mplb_t* h0 = hs[0];
+  hipStream_t s = h0->stream;
+  if (h0->mode != MPLB_COUPLED) {  // CHE-only lattices step one after another on the stream
+    for (int k = 0; k < nsteps; ++k)
+      for (int i = 0; i < count; ++i) {
+        int rc = enqueue_step(hs[i], s);
+        if (rc) return rc;
+      }
+    return MPLB_OK;
+  }
+  int dev = 0;
+  HIPCHK(h0, hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(h0, MPLB_E_DEVICE, "device index out of range");
+  BatchTable& T = g_tables[dev];
+  size_t bytes = fused_batch_item_bytes(h0->prec) * (size_t)count;
+  if (T.uploaded) HIPCHK(h0, hipEventSynchronize(T.uploaded));  // staging free again
+  if (!T.uploaded) HIPCHK(h0, hipEventCreateWithFlags(&T.uploaded, hipEventDisableTiming));
+  if (T.host_cap < bytes) {
+    if (T.host) HIPCHK(h0, hipHostFree(T.host));
+    T.host = nullptr;
+    T.host_cap = 0;
+    HIPCHK(h0, hipHostMalloc(&T.host, 2 * bytes, hipHostMallocDefault));
+    T.host_cap = 2 * bytes;
+  }
+  if (T.dev_cap < bytes) {
+    if (T.dev) {
+      HIPCHK(h0, hipDeviceSynchronize());
+      HIPCHK(h0, hipFree(T.dev));
+    }
+    T.dev = nullptr;
+    T.dev_cap = 0;
+    HIPCHK(h0, hipMalloc(&T.dev, 2 * bytes));
+    T.dev_cap = 2 * bytes;
+  }
+  int blocks = 0;
+  bool xywall = false;
+  for (int i = 0; i < count; ++i) {
+    mplb_t* h = hs[i];
+    int nb = fused_batch_fill(h->prec, T.host, i, h->G, h->C, h->B, h->cur, blocks);
+    if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
+    blocks += nb;
+    xywall = xywall || h->G.wall_x || h->G.wall_y;
+  }
+  HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
+  HIPCHK(h0, hipEventRecord(T.uploaded, s));
+  for (int k = 0; k < nsteps; ++k) HIPCHK(h0, launch_fused_many(h0->prec, xywall, T.dev, count, blocks, k & 1, s));
+  bool check = false;
+  for (int i = 0; i < count; ++i) {
+    mplb_t* h = hs[i];
+    long before = h->step;
+    h->step += nsteps;
+    if (nsteps & 1) h->cur = 1 - h->cur;
+    if (h->check_interval > 0 && h->step / h->check_interval != before / h->check_interval) check = true;
+  }
+  if (check)
     for (int i = 0; i < count; ++i) {
-      int rc = enqueue_step(hs[i], s);
+      int rc = check_flag(hs[i]);
       if (rc) return rc;
     }
   return MPLB_OK;

@@ -1,0 +1,166 @@
+"""Continuous-batching serving loop for many independent simulations.
+
+Requests (a workload and a step target) arrive over time.  The loop admits
+them as slots while their device bytes fit an HBM budget, keeps every
+admitted lattice resident, and advances all of them together: one batched
+step kernel per time step covers every active lattice (``mplb_step_many``).
+A lattice that reaches its target is read out (fields to the host) and freed,
+which makes room for the next admissions.  Requests that arrive while others
+are on the GPU join at the next chunk boundary.
+
+The back-to-back reference runs the same requests one at a time, in arrival
+order, with the same chunking.
+
+    python -m paper_1507_07294_amd.serve [--requests 64] [--steps 400] [--budget-gb 16]
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import dataclasses
+import json
+import sys
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import mplb
+from . import workloads as wl
+
+READ_FIELDS = ("phi", "ux", "uy", "uz", "p")
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    admitted: float
+    completed: float
+    lups: int
+    fields: Optional[Dict[str, np.ndarray]] = None
+
+    @property
+    def latency(self) -> float:
+        return self.completed - self.arrival
+
+
+def _required(req, precision):
+    nx, ny, nz = req.workload.shape
+    return mplb.mplb_required_bytes(nx, ny, nz, mplb.PRECISIONS[precision], mplb.MPLB_COUPLED)
+
+
+def _summary(results: List[Result], t_first: float, t_last: float):
+    lat = np.array([r.latency for r in results])
+    lups = sum(r.lups for r in results)
+    span = max(t_last - t_first, 1e-9)
+    return {"requests": len(results), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_s": float(lat.mean()), "makespan_s": span, "aggregate_MLUPS": lups / span / 1e6}
+
+
+class Server:
+    """Admits requests by HBM budget and advances all resident lattices with
+    batched steps, `chunk` steps at a time."""
+
+    def __init__(self, precision="f32", budget_bytes=16e9, chunk=50, keep_fields=False):
+        self.precision = precision
+        self.budget = float(budget_bytes)
+        self.chunk = int(chunk)
+        self.keep_fields = keep_fields
+        self.peak_bytes = 0
+        self.batch_sizes: List[int] = []
+
+    def run(self, trace, realtime=True):
+        t0 = time.perf_counter()
+        pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
+        waiting = collections.deque()
+        active = []  # [req, lattice, done, admitted, bytes]
+        used = 0
+        results: List[Result] = []
+        while pending or waiting or active:
+            now = time.perf_counter() - t0
+            while pending and (not realtime or pending[0].arrival <= now):
+                waiting.append(pending.popleft())
+            while waiting:
+                req = waiting[0]
+                need = _required(req, self.precision)
+                if need > self.budget:
+                    raise ValueError(f"request {req.rid} needs {need} B, more than the budget")
+                if used + need > self.budget:
+                    break
+                waiting.popleft()
+                lt = mplb.from_workload(req.workload, self.precision)
+                used += need
+                self.peak_bytes = max(self.peak_bytes, used)
+                active.append([req, lt, 0, time.perf_counter() - t0, need])
+            if not active:
+                if pending:
+                    time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.01)))
+                continue
+            k = min(self.chunk, min(a[0].steps - a[2] for a in active))
+            mplb.mplb_step_many([a[1] for a in active], k)
+            self.batch_sizes.append(len(active))
+            still = []
+            for a in active:
+                a[2] += k
+                if a[2] >= a[0].steps:
+                    fields = {f: a[1].read(f) for f in READ_FIELDS}  # synchronises
+                    done = time.perf_counter() - t0
+                    results.append(Result(a[0].rid, a[0].arrival, a[3], done, a[0].workload.nodes * a[0].steps,
+                                          fields if self.keep_fields else None))
+                    a[1].destroy()
+                    used -= a[4]
+                else:
+                    still.append(a)
+            active = still
+        t_last = max(r.completed for r in results)
+        t_first = min(r.arrival for r in results)
+        return results, _summary(results, t_first, t_last)
+
+
+def run_back_to_back(trace, precision="f32", chunk=50, realtime=True, keep_fields=False):
+    """The same requests one at a time in arrival order (each alone on the GPU)."""
+    t0 = time.perf_counter()
+    results = []
+    for req in sorted(trace, key=lambda r: r.arrival):
+        if realtime:
+            wait = req.arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+        start = time.perf_counter() - t0
+        lt = mplb.from_workload(req.workload, precision)
+        done = 0
+        while done < req.steps:
+            k = min(chunk, req.steps - done)
+            lt.step(k)
+            done += k
+        fields = {f: lt.read(f) for f in READ_FIELDS}
+        end = time.perf_counter() - t0
+        results.append(Result(req.rid, req.arrival, start, end, req.workload.nodes * req.steps,
+                              fields if keep_fields else None))
+        lt.destroy()
+    t_last = max(r.completed for r in results)
+    t_first = min(r.arrival for r in results)
+    return results, _summary(results, t_first, t_last)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--requests", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--gap-ms", type=float, default=5.0, help="mean Poisson inter-arrival time")
+    ap.add_argument("--budget-gb", type=float, default=16.0)
+    ap.add_argument("--chunk", type=int, default=50)
+    ap.add_argument("--precision", default="f32")
+    args = ap.parse_args(argv)
+    trace = wl.serving_trace(n_requests=args.requests, steps=args.steps, mean_gap_s=args.gap_ms / 1e3)
+    srv = Server(args.precision, args.budget_gb * 1e9, args.chunk)
+    _, mix = srv.run(trace)
+    _, b2b = run_back_to_back(trace, args.precision, args.chunk)
+    print(json.dumps({"serving": mix, "back_to_back": b2b, "peak_bytes": srv.peak_bytes,
+                      "mean_batch": float(np.mean(srv.batch_sizes))}))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

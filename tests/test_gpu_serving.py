@@ -1,0 +1,63 @@
+"""Serving loop on the GPU: every result of a batched, budget-limited mix is
+bitwise the same as the simulation run alone, and the budget holds."""
+import numpy as np
+import pytest
+
+from paper_1507_07294_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+def _trace():
+    reqs = []
+    specs = [("droplet", 32, 90), ("rt", 32, 70), ("droplet", 48, 110), ("droplet", 32, 50),
+             ("rt", 32, 130), ("droplet", 40, 60), ("rt", 24, 80), ("droplet", 32, 100)]
+    for rid, (kind, n, steps) in enumerate(specs):
+        if kind == "droplet":
+            w = wl.static_droplet(n=n, R=n / 4, ratio=2.0 + rid)
+        else:
+            w = wl.rayleigh_taylor(W=n, Re=256.0)
+        reqs.append(wl.Request(rid, 0.0, kind, w.shape, w, steps))
+    return reqs
+
+
+def test_mix_equals_alone_and_budget_holds():
+    from paper_1507_07294_amd import mplb
+    from paper_1507_07294_amd.serve import Server
+    trace = _trace()
+    sizes = [mplb.mplb_required_bytes(*r.workload.shape, mplb.MPLB_F32, mplb.MPLB_COUPLED) for r in trace]
+    budget = sorted(sizes)[-1] + sorted(sizes)[-2] + 1  # about two lattices at a time: admission waits
+    srv = Server("f32", budget, chunk=40, keep_fields=True)
+    results, summary = srv.run(trace, realtime=False)
+    print(f"\n[serving] {summary} peak={srv.peak_bytes} budget={budget} batches={srv.batch_sizes}", flush=True)
+    assert srv.peak_bytes <= budget
+    assert max(srv.batch_sizes) >= 2  # requests really ran together
+    assert len(results) == len(trace)
+    for res in results:
+        req = trace[res.rid]
+        lt = mplb.from_workload(req.workload, "f32")
+        lt.step(req.steps)
+        for f, v in res.fields.items():
+            assert np.array_equal(v, lt.read(f)), (res.rid, f)
+        lt.destroy()
+
+
+def test_step_many_mixed_walls_and_parity():
+    """Lattices at different step parities and with walls on x or y batch
+    together correctly."""
+    from paper_1507_07294_amd import mplb
+    ws = [wl.perturbed_case((20, 18, 16), (0, 0, 1), 91), wl.perturbed_case((17, 21, 15), (1, 0, 0), 92),
+          wl.perturbed_case((33, 9, 12), (0, 1, 1), 93)]
+    alone = []
+    for i, w in enumerate(ws):
+        g = mplb.from_workload(w, "f32")
+        g.step(13 + i)
+        alone.append({k: g.read(k) for k in ("phi", "ux", "p")})
+        g.destroy()
+    mix = [mplb.from_workload(w, "f32") for w in ws]
+    mix[1].step(1)
+    mix[2].step(2)
+    mplb.mplb_step_many(mix, 13)
+    for g, ref in zip(mix, alone):
+        for k, v in ref.items():
+            assert np.array_equal(g.read(k), v), k

@@ -1,0 +1,87 @@
+"""Host logic of the serving loop with a stand-in backend (CPU only):
+admission by budget, FIFO order, every request completes once, batching."""
+import types
+
+import pytest
+
+from paper_1507_07294_amd import serve
+from paper_1507_07294_amd import workloads as wl
+
+
+class FakeLattice:
+    def __init__(self, req):
+        self.req = req
+        self.steps = 0
+        self.alive = True
+
+    def step(self, k):
+        self.steps += k
+
+    def read(self, f):
+        return self.steps
+
+    def destroy(self):
+        self.alive = False
+
+
+@pytest.fixture
+def fake(monkeypatch):
+    state = types.SimpleNamespace(live=0, peak=0, batches=[])
+
+    def from_workload(w, precision):
+        state.live += 1
+        state.peak = max(state.peak, state.live)
+        lt = FakeLattice(w)
+        orig = lt.destroy
+
+        def destroy():
+            state.live -= 1
+            orig()
+        lt.destroy = destroy
+        return lt
+
+    def step_many(lts, k):
+        state.batches.append(len(lts))
+        for lt in lts:
+            lt.step(k)
+
+    monkeypatch.setattr(serve.mplb, "from_workload", from_workload)
+    monkeypatch.setattr(serve.mplb, "mplb_step_many", step_many)
+    monkeypatch.setattr(serve, "_required", lambda req, precision: req.workload.nodes * 100)
+    return state
+
+
+def _trace(n=12):
+    out = []
+    for i in range(n):
+        w = wl.static_droplet(n=8 + 4 * (i % 3), R=2.0)
+        out.append(wl.Request(i, 0.0, "droplet", w.shape, w, 10 + 7 * i))
+    return out
+
+
+def test_budget_limits_residency(fake):
+    trace = _trace()
+    budget = 3 * 16 ** 3 * 100  # three of the largest boxes
+    srv = serve.Server("f32", budget, chunk=5, keep_fields=True)
+    results, summary = srv.run(trace, realtime=False)
+    assert srv.peak_bytes <= budget
+    assert fake.live == 0
+    assert sorted(r.rid for r in results) == list(range(len(trace)))
+    for r in results:
+        assert r.fields["phi"] == trace[r.rid].steps  # stepped exactly to its target
+    assert max(fake.batches) > 1 and summary["requests"] == len(trace)
+
+
+def test_request_over_budget_is_rejected(fake):
+    trace = _trace(2)
+    srv = serve.Server("f32", 10, chunk=5)
+    with pytest.raises(ValueError):
+        srv.run(trace, realtime=False)
+
+
+def test_back_to_back_runs_one_at_a_time(fake):
+    trace = _trace(5)
+    results, summary = serve.run_back_to_back(trace, chunk=4, realtime=False, keep_fields=True)
+    assert fake.peak == 1
+    assert [r.rid for r in results] == list(range(5))
+    assert all(r.fields["phi"] == trace[r.rid].steps for r in results)
