@@ -26,7 +26,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per lattice update (22 populations + 3-word (phi u)
 # history, each read and written once), per storage mode
 ALGO_BYTES = {"f64": 400, "f32": 200, "f16": 116, "bf16": 116}
-CHE_ALGO_BYTES = {"f64": 2 * 8 * 10, "f32": 2 * 4 * 10}  # 7 populations + 3-word history
+CHE_ALGO_BYTES = {"f64": 2 * 8 * 8, "f32": 2 * 4 * 8}  # 7 populations + phi of the previous level
 
 
 def parse():
@@ -213,12 +213,18 @@ def main():
         trace = wl.serving_trace(n_requests=args.serving_requests, steps=args.serving_steps, mean_gap_s=0.003)
         srv = serve.Server("f32", 16e9, chunk=50)
         _, mix = srv.run(trace)
+        mplb.mplb_set_step_many_graphs(False)  # the same batched loop, steps launched one by one
+        try:
+            _, mix_nog = serve.Server("f32", 16e9, chunk=50).run(trace)
+        finally:
+            mplb.mplb_set_step_many_graphs(True)
         _, b2b = serve.run_back_to_back(trace, "f32", chunk=50)
         result["serving"] = {
             "trace": f"{args.serving_requests} requests, Poisson arrivals (mean gap 3 ms, seed 20261202), half "
                      f"droplets (32^3..128^3) half Rayleigh-Taylor (W = 32..64), {args.serving_steps} steps each, "
                      "FP32, HBM budget 16 GB",
             "batched": {k: round(v, 4) for k, v in mix.items()},
+            "batched_without_graphs": {k: round(v, 4) for k, v in mix_nog.items()},
             "back_to_back": {k: round(v, 4) for k, v in b2b.items()},
             "mean_batch": round(float(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes))), 2),
             "peak_bytes": srv.peak_bytes}

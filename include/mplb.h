@@ -87,7 +87,8 @@ typedef struct mplb_params {
 typedef struct mplb_s mplb_t;
 
 /* Device bytes a lattice needs (populations of two time levels, the
- * (phi u) history, phi, mu, a read-out buffer and reduction scratch). */
+ * (phi u) history (3 words per node; CHE-only: phi, 1 word), phi, mu, a
+ * read-out buffer and reduction scratch). */
 int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes);
 
 /* Create a lattice of nx*ny*nz nodes (each >= 1) with bc[a] in
@@ -108,7 +109,10 @@ int mplb_set_stream(mplb_t* h, void* hip_stream);
 int mplb_set_params(mplb_t* h, const mplb_params* p);
 
 /* CHE-only lattices: the velocity prescribed at step n.  u_field (3N, used
- * by MPLB_VEL_FIELD only) is copied.  U and T as in Eqs. 37 and 41. */
+ * by MPLB_VEL_FIELD only) is copied.  U and T as in Eqs. 37 and 41.  Call it
+ * before mplb_init: the time derivative of Eq. 34 is formed from phi of the
+ * previous level and the prescribed u there, so the velocity is fixed for the
+ * run; after init it returns MPLB_E_STATE. */
 int mplb_set_velocity(mplb_t* h, int kind, const double* u_field, double U, double T);
 
 /* Equilibrium start (an initial state the paper leaves open): mu_0 from
@@ -140,11 +144,28 @@ int mplb_read(mplb_t* h, int field, double* out);
  * if any population is non-finite. */
 int mplb_totals(mplb_t* h, double out[7]);
 
+/* Interface extremes of a layered run at the current level (the spike tip
+ * and bubble front of a heavy-over-light Rayleigh-Taylor layer, Sec. III C):
+ * out[0] and out[1] are the lowest and the highest z at which phi changes
+ * sign between two adjacent layers of one column, located by linear
+ * interpolation, with layer k at z = k + 1/2 (phi = 0 counts as positive).
+ * Both are -1 when no column crosses.  A periodic z axis is scanned from
+ * layer 0 to nz-1 without wrapping.  Synchronises; does not change the
+ * state. */
+int mplb_front(mplb_t* h, double out[2]);
+
 /* Advance `count` lattices by nsteps each with batched launches: one kernel
- * per stage covers every lattice (continuous-batching serving).  All handles
- * must be initialised, share one precision and mode, and use the first
- * handle's stream. */
+ * per step covers every coupled lattice (continuous-batching serving); the
+ * nsteps launches are replayed as one HIP graph, cached while the batch keeps
+ * its shape.  Each lattice computes exactly what mplb_step computes for it.
+ * All handles must be initialised, share one precision and mode, and use the
+ * first handle's stream.  Not thread-safe across calls on one device.
+ * CHE-only lattices are stepped one after another. */
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
+
+/* Whether mplb_step_many replays its steps as a graph (enable != 0, the
+ * default) or launches them one by one; process-wide, for measurement. */
+int mplb_set_step_many_graphs(int enable);
 
 /* Bytes of a checkpoint (raw state in storage precision plus the step
  * counter); mplb_checkpoint writes it to host memory, mplb_restore reads one

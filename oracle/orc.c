@@ -702,6 +702,28 @@ int orc_totals(orc_t* s, double out[7]) {
   return ORC_OK;
 }
 
+int orc_front(orc_t* s, double out[2]) {
+  if (!s || !out) return ORC_E_INVAL;
+  if (!s->have_init) return ORC_E_STATE;
+  compute_macro(s);
+  int found = 0;
+  double lo = 0.0, hi = 0.0;
+  for (int y = 0; y < s->n[1]; ++y)
+    for (int x = 0; x < s->n[0]; ++x)
+      for (int z = 0; z + 1 < s->n[2]; ++z) {
+        double a = s->phi[idx(s, x, y, z)], b = s->phi[idx(s, x, y, z + 1)];
+        if ((a < 0.0) == (b < 0.0)) continue;
+        /* phi is linear between the layer centres z + 1/2 and z + 3/2 */
+        double zc = (z + 0.5) + a / (a - b);
+        if (!found || zc < lo) lo = zc;
+        if (!found || zc > hi) hi = zc;
+        found = 1;
+      }
+  out[0] = found ? lo : -1.0;
+  out[1] = found ? hi : -1.0;
+  return ORC_OK;
+}
+
 int orc_get_state(const orc_t* s, double* f, double* g, double* phiu) {
   if (!s) return ORC_E_INVAL;
   if (f) memcpy(f, s->f, 7 * s->N * sizeof(double));

@@ -61,6 +61,12 @@ long orc_step_count(const orc_t* s);
 int orc_read(orc_t* s, int field, double* out);
 /* out[7] = { sum phi, sum_x sum_i c_i g_i (3), sum F = F_s + F_a + G (3) }. */
 int orc_totals(orc_t* s, double out[7]);
+/* Spike tip and bubble front of a heavy-over-light layer (Sec. III C):
+ * out[0], out[1] = lowest and highest z where phi changes sign between
+ * adjacent layers of a column (layer k at z = k + 1/2, linear interpolation,
+ * phi = 0 counts as positive); -1, -1 when no column crosses.  Layers are
+ * scanned 0..nz-1 without wrapping. */
+int orc_front(orc_t* s, double out[2]);
 /* Populations at the current level (after streaming): f[7N], g[15N], phiu[3N]
  * holds (phi u) of the previous level.  Any pointer may be NULL. */
 int orc_get_state(const orc_t* s, double* f, double* g, double* phiu);

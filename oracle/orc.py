@@ -61,6 +61,7 @@ def lib():
         L.orc_step_count.argtypes = [C.c_void_p]
         L.orc_read.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_totals.argtypes = [C.c_void_p, dp]
+        L.orc_front.argtypes = [C.c_void_p, dp]
         L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_last_error.restype = C.c_char_p
@@ -171,6 +172,12 @@ class Oracle:
     def totals(self):
         out = np.empty(7, dtype=np.float64)
         self._chk(lib().orc_totals(self._h, _dp(out)))
+        return out
+
+    def front(self):
+        """(lowest, highest) z of a zero crossing of phi along z; (-1, -1) if none."""
+        out = np.empty(2, dtype=np.float64)
+        self._chk(lib().orc_front(self._h, _dp(out)))
         return out
 
     def get_state(self):

@@ -31,6 +31,7 @@ struct Coef {
   int vel_kind;           // CHE-only prescribed velocity kind
   T velU;
   T vel_ct;               // cos(pi t / T) of the current step (deformation flow)
+  T vel_ct_prev;          // the same at the previous level (step 0: the current one)
 };
 
 // Compute type T, storage of f_0 (S0) and of f_1..f_6 and g (S).
@@ -45,7 +46,8 @@ template <> struct Prec<MPLB_F32_BF16> { using T = float; using S0 = float; usin
 struct Bufs {
   void* f[2];
   void* g[2];
-  void* phiu;   // 3 x pitch, T: (phi u) of the previous level
+  void* phiu;   // T: (phi u) of the previous level, 3 x pitch (coupled);
+                //    phi of the previous level, 1 x pitch (CHE-only: u is prescribed)
   void* phi;    // pitch, T
   void* mu;     // pitch, T
   void* ufield; // 3 x pitch, T (CHE-only, prescribed field)

@@ -165,9 +165,12 @@ __device__ inline void grad_lap(const Geo& G, const T* chi, int x, int y, int z,
 
 // Prescribed velocity of the interface-tracking runs: a constant field,
 // Zalesak's rotation (Eq. 37) or the deformation flow (Eq. 41 times
-// cos(pi t / T), the cosine passed in as C.vel_ct).
+// cos(pi t / T), the cosine passed in as C.vel_ct).  When up is given it
+// receives the velocity of the previous level (the same except for the
+// deformation flow, whose cosine there is C.vel_ct_prev).
 template <class T>
-__device__ inline void presc_u(const Geo& G, const Coef<T>& C, const T* uf, int x, int y, int z, int n, T u[3]) {
+__device__ inline void presc_u(const Geo& G, const Coef<T>& C, const T* uf, int x, int y, int z, int n, T u[3],
+                               T* up = nullptr) {
   u[0] = u[1] = u[2] = 0;
   if (C.vel_kind == MPLB_VEL_FIELD) {
     u[0] = uf[n];
@@ -183,11 +186,16 @@ __device__ inline void presc_u(const Geo& G, const Coef<T>& C, const T* uf, int 
     T xh = (T)x / (T)G.nx, yh = (T)y / (T)G.ny, zh = (T)z / (T)G.nz;
     T sx = sin(pi * xh), sy = sin(pi * yh), sz = sin(pi * zh);
     T s2x = sin(2 * pi * xh), s2y = sin(2 * pi * yh), s2z = sin(2 * pi * zh);
-    T U = C.velU, ct = C.vel_ct;
-    u[0] = 2 * U * sx * sx * s2y * s2z * ct;
-    u[1] = -U * s2x * sy * sy * s2z * ct;
-    u[2] = -U * s2x * s2y * sz * sz * ct;
+    T U = C.velU;
+    T b[3] = {2 * U * sx * sx * s2y * s2z, -U * s2x * sy * sy * s2z, -U * s2x * s2y * sz * sz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      u[a] = b[a] * C.vel_ct;
+      if (up) up[a] = b[a] * C.vel_ct_prev;
+    }
+    return;
   }
+  if (up) up[0] = u[0], up[1] = u[1], up[2] = u[2];
 }
 
 // ------------------------------------------------------------ node physics

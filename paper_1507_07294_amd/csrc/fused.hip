@@ -472,15 +472,14 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     T phi = phi_of(f);
     T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c);
     T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
-    T u[3];
-    presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u);
+    T u[3], up[3];
+    presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
+    // Eq. 34 with u known at both levels: only phi of the previous level is kept
+    const T phip = hist[n];
+    hist[n] = phi;
     T dphiu[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      T pu = phi * u[a];
-      dphiu[a] = pu - hist[(size_t)a * G.pitch + n];
-      hist[(size_t)a * G.pitch + n] = pu;
-    }
+    for (int a = 0; a < 3; ++a) dphiu[a] = phi * u[a] - phip * up[a];
     collide_che(C, f, phi, mu, u, dphiu);
 #pragma unroll
     for (int i = 0; i < 7; ++i) L::stf(fo, G.pitch, i, n, f[i]);
@@ -497,7 +496,7 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
   for (int a = 0; a < 3; ++a) o.grav[a] = (T)c.grav[a];
   for (int i = 0; i < 7; ++i) o.sf[i] = (T)c.sf[i];
   for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
-  o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct;
+  o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
   return o;
 }
 
@@ -548,6 +547,37 @@ hipError_t many_impl2(const void* dtab, int count, int total_blocks, int flip, h
   hipLaunchKernelGGL((k_fused_many<P, kTY, XYWALL>), dim3((unsigned)total_blocks), dim3(kTX * kTY), 0, s,
                      (const BatchItem<T>*)dtab, count, flip);
   return hipGetLastError();
+}
+
+// nsteps batched steps as a chain of kernel nodes (flip alternating), built
+// directly rather than by stream capture so that it works on any stream.
+template <int P, bool XYWALL>
+hipError_t many_graph2(const void* dtab, int count, int total_blocks, int nsteps, hipGraph_t* out) {
+  hipGraph_t g = nullptr;
+  hipError_t e = hipGraphCreate(&g, 0);
+  if (e != hipSuccess) return e;
+  hipGraphNode_t prev = nullptr;
+  for (int k = 0; k < nsteps && e == hipSuccess; ++k) {
+    int flip = k & 1;
+    const void* tab = dtab;
+    void* args[] = {(void*)&tab, (void*)&count, (void*)&flip};
+    hipKernelNodeParams kp{};
+    kp.func = (void*)k_fused_many<P, kTY, XYWALL>;
+    kp.gridDim = dim3((unsigned)total_blocks);
+    kp.blockDim = dim3(kTX * kTY);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddKernelNode(&node, g, prev ? &prev : nullptr, prev ? 1 : 0, &kp);
+    prev = node;
+  }
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return e;
+  }
+  *out = g;
+  return hipSuccess;
 }
 
 template <int P>
@@ -606,6 +636,21 @@ hipError_t launch_fused_many(int P, bool xywall, const void* dtab, int count, in
     default: return hipErrorInvalidValue;
   }
 #undef MPLB_MANY
+}
+
+hipError_t build_fused_many_graph(int P, bool xywall, const void* dtab, int count, int total_blocks, int nsteps,
+                                  hipGraph_t* out) {
+#define MPLB_GRAPH(PP)                                                                   \
+  return xywall ? many_graph2<PP, true>(dtab, count, total_blocks, nsteps, out)        \
+                : many_graph2<PP, false>(dtab, count, total_blocks, nsteps, out);
+  switch (P) {
+    case MPLB_F64: MPLB_GRAPH(MPLB_F64)
+    case MPLB_F32: MPLB_GRAPH(MPLB_F32)
+    case MPLB_F32_F16: MPLB_GRAPH(MPLB_F32_F16)
+    case MPLB_F32_BF16: MPLB_GRAPH(MPLB_F32_BF16)
+    default: return hipErrorInvalidValue;
+  }
+#undef MPLB_GRAPH
 }
 
 }  // namespace mplb

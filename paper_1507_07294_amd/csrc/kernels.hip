@@ -13,6 +13,7 @@
 //                 for read-out, totals and the initial state
 //   k_macro       one macroscopic field at the current level
 //   k_totals      FP64 sums of phi, momentum and force, non-finite count
+//   k_front       lowest and highest zero crossing of phi along z
 //   k_init        equilibrium initial state (Eqs. 5, 21)
 #include <cmath>
 
@@ -178,6 +179,71 @@ __global__ void __launch_bounds__(kBlock) k_totals_final(double* red, int nslots
   }
 }
 
+// Interface extremes along z (Rayleigh-Taylor spike tip and bubble front):
+// each thread scans columns (x, y) upward through the phi array, locating
+// sign changes of phi between layers k and k+1 by linear interpolation at
+// z = k + 1/2 + phi_k / (phi_k - phi_{k+1}) (layer k sits at k + 1/2); the
+// block keeps the lowest and highest crossing in slots 0 and 1 of its 8.
+template <class T>
+__global__ void __launch_bounds__(kBlock) k_front(Geo G, Bufs B) {
+  const T* phi = (const T*)B.phi;
+  const int cols = G.nx * G.ny;
+  const size_t plane = (size_t)cols;
+  double lo = INFINITY, hi = -INFINITY;
+  for (int c = blockIdx.x * kBlock + threadIdx.x; c < cols; c += gridDim.x * kBlock) {
+    double a = (double)phi[c];
+    for (int k = 0; k + 1 < G.nz; ++k) {
+      const double b = (double)phi[(size_t)(k + 1) * plane + c];
+      if ((a < 0.0) != (b < 0.0)) {
+        const double z = k + 0.5 + a / (a - b);
+        lo = fmin(lo, z);
+        hi = fmax(hi, z);
+      }
+      a = b;
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  __shared__ double part[kBlock / 64][2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) {
+    part[wave][0] = lo;
+    part[wave][1] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kBlock / 64; ++w) {
+      lo = fmin(lo, part[w][0]);
+      hi = fmax(hi, part[w][1]);
+    }
+    B.red[(size_t)blockIdx.x * 8] = lo;
+    B.red[(size_t)blockIdx.x * 8 + 1] = hi;
+  }
+}
+
+// Extremes over the block slots into the final slot; -1 for both when no
+// column crosses.
+__global__ void __launch_bounds__(64) k_front_final(double* red, int nslots) {
+  double lo = INFINITY, hi = -INFINITY;
+  for (int s = threadIdx.x; s < nslots; s += 64) {
+    lo = fmin(lo, red[(size_t)s * 8]);
+    hi = fmax(hi, red[(size_t)s * 8 + 1]);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, o, 64));
+    hi = fmax(hi, __shfl_xor(hi, o, 64));
+  }
+  if (threadIdx.x == 0) {
+    const bool none = !(lo <= hi);
+    red[(size_t)kRedSlots * 8] = none ? -1.0 : lo;
+    red[(size_t)kRedSlots * 8 + 1] = none ? -1.0 : hi;
+  }
+}
+
 template <class T>
 __global__ void __launch_bounds__(kBlock) k_cvt_in(const double* src, T* dst, int N) {
   int n = blockIdx.x * kBlock + threadIdx.x;
@@ -229,7 +295,11 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T
       else Lat<P, packed<P, COUPLED>()>::stg(B.f[cur], B.g[cur], G.pitch, opp(i), n, geq);
     }
   }
-  for (int a = 0; a < 3; ++a) hist[(size_t)a * G.pitch + n] = phi * u[a];
+  if (COUPLED) {
+    for (int a = 0; a < 3; ++a) hist[(size_t)a * G.pitch + n] = phi * u[a];
+  } else {
+    hist[n] = phi;  // CHE-only: the history is phi alone
+  }
 }
 
 // plain streaming copy with 16-byte accesses (bandwidth reference)
@@ -265,7 +335,7 @@ Coef<T> cast_coef(const Coef<double>& c) {
   for (int a = 0; a < 3; ++a) o.grav[a] = (T)c.grav[a];
   for (int i = 0; i < 7; ++i) o.sf[i] = (T)c.sf[i];
   for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
-  o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct;
+  o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
   return o;
 }
 
@@ -337,6 +407,18 @@ hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, co
 
 hipError_t launch_totals(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur, hipStream_t s) {
   MPLB_DISPATCH(P, return totals_impl<PP>(mode, G, C, B, cur, s))
+}
+
+hipError_t launch_front(int P, const Geo& G, const Bufs& B, hipStream_t s) {
+  const int cols = G.nx * G.ny;
+  int blocks = (cols + kBlock - 1) / kBlock;
+  if (blocks > kRedSlots) blocks = kRedSlots;
+  if (P == MPLB_F64) hipLaunchKernelGGL(k_front<double>, dim3(blocks), dim3(kBlock), 0, s, G, B);
+  else hipLaunchKernelGGL(k_front<float>, dim3(blocks), dim3(kBlock), 0, s, G, B);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_front_final, dim3(1), dim3(64), 0, s, B.red, blocks);
+  return hipGetLastError();
 }
 
 hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStream_t s) {

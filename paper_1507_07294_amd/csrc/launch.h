@@ -24,12 +24,19 @@ int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>
                      int block0);
 hipError_t launch_fused_many(int P, bool xywall, const void* dtab, int count, int total_blocks, int flip,
                              hipStream_t s);
+// the same for nsteps steps (flip = k & 1 at step k) as a graph of kernel
+// nodes; the caller instantiates, launches and destroys it
+hipError_t build_fused_many_graph(int P, bool xywall, const void* dtab, int count, int total_blocks, int nsteps,
+                                  hipGraph_t* out);
 // field (MPLB_PHI..MPLB_P) at the current level into B.out (double)
 hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                         int field, hipStream_t s);
 // FP64 totals and non-finite count into B.red[kRedSlots*8 .. +8)
 hipError_t launch_totals(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                          hipStream_t s);
+// lowest and highest z where phi (the B.phi array) crosses 0 along z, into
+// B.red[kRedSlots*8 .. +2) (-1, -1 when there is none)
+hipError_t launch_front(int P, const Geo& G, const Bufs& B, hipStream_t s);
 // dst[n] = (T) B.out[n] for n < N (upload of a host field staged in B.out)
 hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStream_t s);
 // equilibrium initial state into buffer `cur`, from phi, mu and u (held in phiu)

@@ -42,7 +42,8 @@ Plan make_plan(long long N, int prec, int mode) {
   bool pack = mode == MPLB_COUPLED && sS == 2;
   p.f = align_up(p.pitch * s0 + 6 * p.pitch * (pack ? 4 : sS), A);
   p.g = mode == MPLB_COUPLED ? align_up((pack ? 9 : 15) * p.pitch * sS, A) : 0;
-  p.phiu = align_up(3 * p.pitch * sT, A);
+  // (phi u) history: 3 words (coupled); phi alone where u is prescribed
+  p.phiu = align_up((mode == MPLB_COUPLED ? 3 : 1) * p.pitch * sT, A);
   p.phi = align_up(p.pitch * sT, A);
   p.mu = align_up(p.pitch * sT, A);
   p.ufield = mode == MPLB_CHE_ONLY ? align_up(3 * p.pitch * sT, A) : 0;
@@ -177,7 +178,7 @@ int mplb_create(int nx, int ny, int nz, const int bc[3], int precision, int mode
   h->B.red = (double*)p; p += P.red;
   h->B.flag = (int*)p; p += P.flag;
   h->C.vel_kind = MPLB_VEL_ZERO;
-  h->C.vel_ct = 1.0;
+  h->C.vel_ct = h->C.vel_ct_prev = 1.0;
   *out = h;
   return MPLB_OK;
 }
@@ -245,6 +246,8 @@ static int upload_field(mplb_t* h, const double* src, void* dst) {
 int mplb_set_velocity(mplb_t* h, int kind, const double* u_field, double U, double T) {
   if (!h) return MPLB_E_INVAL;
   if (h->mode != MPLB_CHE_ONLY) return fail(h, MPLB_E_STATE, "prescribed velocity needs a CHE-only lattice");
+  if (h->have_init)  // the history holds phi only and relies on u at the previous level being known
+    return fail(h, MPLB_E_STATE, "set_velocity after init");
   if (kind < MPLB_VEL_ZERO || kind > MPLB_VEL_DEFORM || (kind == MPLB_VEL_FIELD && !u_field) ||
       (kind == MPLB_VEL_DEFORM && !(T > 0.0)) || !std::isfinite(U))
     return fail(h, MPLB_E_INVAL, "invalid velocity specification");
@@ -269,6 +272,15 @@ static double deform_ct(const mplb_t* h, long n) {
   return std::cos(pi * t / h->velT);
 }
 
+// Time factors of the prescribed velocity for the step that starts at level
+// h->step: the current level and the previous one (level 0 at the first step,
+// where the history is phi_0 u_0).
+static void set_vel_time(mplb_t* h) {
+  if (h->mode != MPLB_CHE_ONLY || h->C.vel_kind != MPLB_VEL_DEFORM) return;
+  h->C.vel_ct = deform_ct(h, h->step);
+  h->C.vel_ct_prev = deform_ct(h, h->step > 0 ? h->step - 1 : 0);
+}
+
 int mplb_init(mplb_t* h, const double* phi0, const double* u0) {
   if (!h || !phi0) return MPLB_E_INVAL;
   if (!h->have_params) return fail(h, MPLB_E_STATE, "init before set_params");
@@ -287,7 +299,7 @@ int mplb_init(mplb_t* h, const double* phi0, const double* u0) {
     }
   }
   HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
-  h->C.vel_ct = 1.0;
+  h->C.vel_ct = h->C.vel_ct_prev = 1.0;
   h->cur = 0;
   HIPCHK(h, launch_init(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream));
   HIPCHK(h, launch_fill_int(h->B.flag, 0, 1, h->stream));
@@ -307,7 +319,7 @@ static int check_flag(mplb_t* h) {
 
 // Enqueue one step of lattice h on stream s.
 static int enqueue_step(mplb_t* h, hipStream_t s) {
-  if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+  set_vel_time(h);
   HIPCHK(h, launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s));
   h->cur = 1 - h->cur;
   h->step++;
@@ -337,7 +349,7 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
   int rc = MPLB_OK;
   for (int k = 0; k < nsteps && rc == MPLB_OK; ++k) {
     hipEvent_t* e = &ev[4 * (size_t)k];
-    if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+    set_vel_time(h);
     hipError_t err = hipEventRecord(e[0], h->stream);
     if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
     if (err == hipSuccess) err = hipEventRecord(e[2], h->stream);
@@ -363,6 +375,16 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
   return rc;
 }
 
+// Instantiated graph of a chunk of batched steps, reused while the batch
+// keeps its shape (precision, walls, item count, block count, steps, table).
+struct ChunkGraph {
+  int prec = -1, xywall = 0, count = 0, blocks = 0, nsteps = 0;
+  const void* table = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned long long used = 0;
+};
+constexpr int kGraphCache = 4;
+
 // Device table of a batched step and its pinned host staging (grow-only,
 // one per device; batched calls on one device are not thread-safe).
 struct BatchTable {
@@ -370,9 +392,53 @@ struct BatchTable {
   size_t dev_cap = 0;
   void* host = nullptr;
   size_t host_cap = 0;
-  hipEvent_t uploaded = nullptr;
+  hipEvent_t uploaded = nullptr;  // host staging consumed
+  hipEvent_t done = nullptr;      // last launches that read the device table
+  ChunkGraph graphs[kGraphCache];
+  unsigned long long clock = 0;
 };
 static BatchTable g_tables[64];
+static bool g_use_graphs = true;
+
+int mplb_set_step_many_graphs(int enable) {
+  g_use_graphs = enable != 0;
+  return MPLB_OK;
+}
+
+// The cached graph for this chunk shape, built and instantiated on a miss
+// (replacing the least recently used entry).
+static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, int count, int blocks, int nsteps,
+                       hipGraphExec_t* out) {
+  ChunkGraph* slot = nullptr;
+  for (auto& c : T.graphs)
+    if (c.exec && c.prec == h0->prec && c.xywall == (int)xywall && c.count == count && c.blocks == blocks &&
+        c.nsteps == nsteps && c.table == T.dev)
+      slot = &c;
+  if (!slot) {
+    slot = &T.graphs[0];
+    for (auto& c : T.graphs)
+      if (!c.exec || c.used < slot->used) slot = &c;
+    if (slot->exec) HIPCHK(h0, hipGraphExecDestroy(slot->exec));
+    slot->exec = nullptr;
+    hipGraph_t g = nullptr;
+    HIPCHK(h0, build_fused_many_graph(h0->prec, xywall, T.dev, count, blocks, nsteps, &g));
+    hipError_t e = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      slot->exec = nullptr;
+      return fail(h0, MPLB_E_DEVICE, "graph instantiate: %s", hipGetErrorString(e));
+    }
+    slot->prec = h0->prec;
+    slot->xywall = xywall;
+    slot->count = count;
+    slot->blocks = blocks;
+    slot->nsteps = nsteps;
+    slot->table = T.dev;
+  }
+  slot->used = ++T.clock;
+  *out = slot->exec;
+  return MPLB_OK;
+}
 
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   if (!hs || count < 0 || nsteps < 0) return MPLB_E_INVAL;
@@ -402,6 +468,7 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   size_t bytes = fused_batch_item_bytes(h0->prec) * (size_t)count;
   if (T.uploaded) HIPCHK(h0, hipEventSynchronize(T.uploaded));  // staging free again
   if (!T.uploaded) HIPCHK(h0, hipEventCreateWithFlags(&T.uploaded, hipEventDisableTiming));
+  if (!T.done) HIPCHK(h0, hipEventCreateWithFlags(&T.done, hipEventDisableTiming));
   if (T.host_cap < bytes) {
     if (T.host) HIPCHK(h0, hipHostFree(T.host));
     T.host = nullptr;
@@ -428,9 +495,19 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
     blocks += nb;
     xywall = xywall || h->G.wall_x || h->G.wall_y;
   }
+  // the previous batched launches (perhaps on another stream) still read the table
+  HIPCHK(h0, hipStreamWaitEvent(s, T.done, 0));
   HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
   HIPCHK(h0, hipEventRecord(T.uploaded, s));
-  for (int k = 0; k < nsteps; ++k) HIPCHK(h0, launch_fused_many(h0->prec, xywall, T.dev, count, blocks, k & 1, s));
+  if (g_use_graphs && nsteps > 1) {
+    hipGraphExec_t ex = nullptr;
+    int rc = chunk_graph(h0, T, xywall, count, blocks, nsteps, &ex);
+    if (rc) return rc;
+    HIPCHK(h0, hipGraphLaunch(ex, s));
+  } else {
+    for (int k = 0; k < nsteps; ++k) HIPCHK(h0, launch_fused_many(h0->prec, xywall, T.dev, count, blocks, k & 1, s));
+  }
+  HIPCHK(h0, hipEventRecord(T.done, s));
   bool check = false;
   for (int i = 0; i < count; ++i) {
     mplb_t* h = hs[i];
@@ -450,7 +527,7 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
 static int prepare_macro(mplb_t* h) {
   HIPCHK(h, launch_phi(h->prec, h->mode, h->G, h->B, h->cur, h->stream));
   if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
-  if (h->mode == MPLB_CHE_ONLY && h->C.vel_kind == MPLB_VEL_DEFORM) h->C.vel_ct = deform_ct(h, h->step);
+  set_vel_time(h);
   return MPLB_OK;
 }
 
@@ -461,6 +538,17 @@ int mplb_read(mplb_t* h, int field, double* out) {
   if (rc) return rc;
   HIPCHK(h, launch_macro(h->prec, h->mode, h->G, h->C, h->B, h->cur, field, h->stream));
   HIPCHK(h, hipMemcpyAsync(out, h->B.out, (size_t)h->G.N * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MPLB_OK;
+}
+
+int mplb_front(mplb_t* h, double out[2]) {
+  if (!h || !out) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "front before init");
+  HIPCHK(h, launch_phi(h->prec, h->mode, h->G, h->B, h->cur, h->stream));
+  HIPCHK(h, launch_front(h->prec, h->G, h->B, h->stream));
+  HIPCHK(h, hipMemcpyAsync(out, h->B.red + (size_t)kRedSlots * 8, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   return MPLB_OK;
 }

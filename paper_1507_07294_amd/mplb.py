@@ -57,6 +57,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"libmplb.so is not built ({LIB_PATH}); run paper_1507_07294_amd/build.py")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one; loading torch first makes libmplb bind to that copy, so that
+        # torch's memory and streams and the library share one runtime
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, dp, ip, sz = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int), C.c_size_t
         sig = {
@@ -71,7 +75,9 @@ def lib():
             "mplb_step_count": (C.c_long, [vp]),
             "mplb_read": (C.c_int, [vp, C.c_int, dp]),
             "mplb_totals": (C.c_int, [vp, dp]),
+            "mplb_front": (C.c_int, [vp, dp]),
             "mplb_step_many": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int]),
+            "mplb_set_step_many_graphs": (C.c_int, [C.c_int]),
             "mplb_checkpoint_bytes": (C.c_int, [vp, C.POINTER(sz)]),
             "mplb_checkpoint": (C.c_int, [vp, vp, sz]),
             "mplb_restore": (C.c_int, [vp, vp, sz]),
@@ -224,6 +230,13 @@ class Lattice:
         self._chk(lib().mplb_totals(self._h, _dp(out)))
         return out
 
+    def front(self):
+        """(spike tip, bubble front): lowest and highest z of a zero crossing of
+        phi along z at the current level; (-1, -1) if there is none."""
+        out = np.empty(2, dtype=np.float64)
+        self._chk(lib().mplb_front(self._h, _dp(out)))
+        return out
+
     def try_totals(self):
         out = np.empty(7, dtype=np.float64)
         rc = lib().mplb_totals(self._h, _dp(out))
@@ -268,6 +281,13 @@ def mplb_step_many(lattices, nsteps):
     rc = lib().mplb_step_many(arr, len(lattices), int(nsteps))
     if rc:
         raise MplbError(rc, lib().mplb_last_error(lattices[0].handle).decode() if lattices else "")
+
+
+def mplb_set_step_many_graphs(enable):
+    """Replay batched steps as a graph (True, the default) or launch them one by one."""
+    rc = lib().mplb_set_step_many_graphs(1 if enable else 0)
+    if rc:
+        raise MplbError(rc, "mplb_set_step_many_graphs")
 
 
 def mplb_copy_probe(src, dst, nbytes, stream=None):

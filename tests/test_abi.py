@@ -60,3 +60,20 @@ def test_product_path_has_no_cpu_fallback():
     if not torch.cuda.is_available():
         with pytest.raises(RuntimeError):
             mplb.Lattice((4, 4, 4))
+
+
+def test_binding_uses_a_single_hip_runtime():
+    """torch's bundled HIP runtime and the system one share a soname; the
+    binding loads torch first so that libmplb binds to torch's copy and only
+    one runtime is mapped (a second one would not see torch's device state).
+    Checked in a fresh process where nothing has loaded torch yet."""
+    import sys
+    REPO = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1507_07294_amd import mplb\n"
+            "mplb.mplb_required_bytes(8, 8, 8, mplb.MPLB_F32, mplb.MPLB_COUPLED)\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "print(len({l.split()[-1] for l in maps if 'amdhip64' in l}))\n") % REPO
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

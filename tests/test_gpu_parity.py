@@ -84,6 +84,28 @@ def test_che_only(kind, precision, tol):
     _compare(w, [1, 7, 40], precision, tol, coupled=False)
 
 
+def test_che_only_walls_and_ragged():
+    """CHE-only with bounce-back on every axis and a box that is not a
+    multiple of the tile: phi history, mirror ghosts and walls together."""
+    shape, bc = (37, 11, 19), (1, 1, 1)
+    w = wl.perturbed_case(shape, bc, 22, coupled=False)
+    w.velocity = {"kind": "deformation", "U": 0.03, "T": 0.04}
+    _compare(w, [1, 9, 50], "f64", F64_TOL, coupled=False)
+
+
+def test_che_only_velocity_fixed_after_init():
+    """The CHE-only history holds phi only, so the prescribed velocity cannot
+    change after init."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((8, 8, 8), (0, 0, 0), 23, coupled=False)
+    w.velocity = {"kind": "zalesak", "U": 0.01}
+    g = helpers.gpu_for(w, "f32")
+    with pytest.raises(mplb.MplbError) as ei:
+        g.set_velocity("zero")
+    assert ei.value.code == mplb.MPLB_E_STATE
+    g.destroy()
+
+
 def test_totals_match_oracle():
     w = wl.perturbed_case((17, 19, 23), (0, 0, 0), 31, coupled=True, gravity=(1e-5, 0, -2e-5))
     o = helpers.oracle_for(w)
@@ -95,6 +117,25 @@ def test_totals_match_oracle():
         g.step(1)
         o.step(1)
         assert np.allclose(g.totals()[1:4], tg[1:4] + tg[4:7], rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-3)])
+def test_front_matches_oracle(precision, tol):
+    """Spike tip and bubble front of a small Rayleigh-Taylor box (heavier
+    gravity so the layer moves within the run), GPU against the oracle."""
+    w = wl.rayleigh_taylor(W=24, Re=256.0, sqrt_gW=0.08)
+    print(f"\n[case] front {w.name} prec={precision}", flush=True)
+    o = helpers.oracle_for(w)
+    g = helpers.gpu_for(w, precision)
+    done = 0
+    for n in (0, 40, 300):
+        o.step(n - done)
+        g.step(n - done)
+        done = n
+        fo, fg = o.front(), g.front()
+        print(f"  n={n} oracle={fo} gpu={fg}", flush=True)
+        assert np.all(np.abs(fg - fo) <= tol), (n, fg, fo)
+    assert fo[0] < 24 * 2 - 0.1 * 24  # the spike has moved down
 
 
 def test_nonfinite_reported_with_step_index():
