@@ -22,12 +22,19 @@ hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& 
 size_t fused_batch_item_bytes(int P);
 int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>& C, const Bufs& B, int cur0,
                      int block0);
-hipError_t launch_fused_many(int P, bool xywall, const void* dtab, int count, int total_blocks, int flip,
+// (nt: streaming stores, for batches whose step moves more than
+// kStreamBytes; see fused_step_bytes)
+hipError_t launch_fused_many(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks, int flip,
                              hipStream_t s);
 // the same for nsteps steps (flip = k & 1 at step k) as a graph of kernel
 // nodes; the caller instantiates, launches and destroys it
-hipError_t build_fused_many_graph(int P, bool xywall, const void* dtab, int count, int total_blocks, int nsteps,
-                                  hipGraph_t* out);
+hipError_t build_fused_many_graph(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks,
+                                  int nsteps, hipGraph_t* out);
+// algorithmic bytes one step of an N-node lattice moves (populations and
+// history read and written once)
+size_t fused_step_bytes(int P, int mode, long long N);
+// step traffic above which the step kernels use streaming stores
+size_t fused_stream_threshold();
 // field (MPLB_PHI..MPLB_P) at the current level into B.out (double)
 hipError_t launch_macro(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                         int field, hipStream_t s);

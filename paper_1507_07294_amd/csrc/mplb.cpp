@@ -54,10 +54,12 @@ Plan make_plan(long long N, int prec, int mode) {
   return p;
 }
 
+// Node indices are 32-bit, and the step kernel forms in-plane byte offsets
+// in 32 bits (nx*ny elements of up to 8 bytes).
 bool valid_dims(int nx, int ny, int nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   long long N = (long long)nx * ny * nz;
-  return N < (1LL << 31) - 4096;
+  return N < (1LL << 31) - 4096 && (long long)nx * ny * 8 < (1LL << 32);
 }
 
 const uint64_t kMagic = 0x31303531504c424dULL;  // checkpoint tag
@@ -378,7 +380,7 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
 // Instantiated graph of a chunk of batched steps, reused while the batch
 // keeps its shape (precision, walls, item count, block count, steps, table).
 struct ChunkGraph {
-  int prec = -1, xywall = 0, count = 0, blocks = 0, nsteps = 0;
+  int prec = -1, xywall = 0, nt = 0, count = 0, blocks = 0, nsteps = 0;
   const void* table = nullptr;
   hipGraphExec_t exec = nullptr;
   unsigned long long used = 0;
@@ -407,11 +409,12 @@ int mplb_set_step_many_graphs(int enable) {
 
 // The cached graph for this chunk shape, built and instantiated on a miss
 // (replacing the least recently used entry).
-static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, int count, int blocks, int nsteps,
+static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, int count, int blocks, int nsteps,
                        hipGraphExec_t* out) {
   ChunkGraph* slot = nullptr;
   for (auto& c : T.graphs)
-    if (c.exec && c.prec == h0->prec && c.xywall == (int)xywall && c.count == count && c.blocks == blocks &&
+    if (c.exec && c.prec == h0->prec && c.xywall == (int)xywall && c.nt == (int)nt && c.count == count &&
+        c.blocks == blocks &&
         c.nsteps == nsteps && c.table == T.dev)
       slot = &c;
   if (!slot) {
@@ -421,7 +424,7 @@ static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, int count, int bl
     if (slot->exec) HIPCHK(h0, hipGraphExecDestroy(slot->exec));
     slot->exec = nullptr;
     hipGraph_t g = nullptr;
-    HIPCHK(h0, build_fused_many_graph(h0->prec, xywall, T.dev, count, blocks, nsteps, &g));
+    HIPCHK(h0, build_fused_many_graph(h0->prec, xywall, nt, T.dev, count, blocks, nsteps, &g));
     hipError_t e = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
@@ -430,6 +433,7 @@ static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, int count, int bl
     }
     slot->prec = h0->prec;
     slot->xywall = xywall;
+    slot->nt = nt;
     slot->count = count;
     slot->blocks = blocks;
     slot->nsteps = nsteps;
@@ -488,24 +492,28 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   }
   int blocks = 0;
   bool xywall = false;
+  size_t step_bytes = 0;
   for (int i = 0; i < count; ++i) {
     mplb_t* h = hs[i];
     int nb = fused_batch_fill(h->prec, T.host, i, h->G, h->C, h->B, h->cur, blocks);
     if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
     blocks += nb;
     xywall = xywall || h->G.wall_x || h->G.wall_y;
+    step_bytes += fused_step_bytes(h->prec, h->mode, h->G.N);
   }
+  const bool nt = step_bytes > fused_stream_threshold();
   // the previous batched launches (perhaps on another stream) still read the table
   HIPCHK(h0, hipStreamWaitEvent(s, T.done, 0));
   HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
   HIPCHK(h0, hipEventRecord(T.uploaded, s));
   if (g_use_graphs && nsteps > 1) {
     hipGraphExec_t ex = nullptr;
-    int rc = chunk_graph(h0, T, xywall, count, blocks, nsteps, &ex);
+    int rc = chunk_graph(h0, T, xywall, nt, count, blocks, nsteps, &ex);
     if (rc) return rc;
     HIPCHK(h0, hipGraphLaunch(ex, s));
   } else {
-    for (int k = 0; k < nsteps; ++k) HIPCHK(h0, launch_fused_many(h0->prec, xywall, T.dev, count, blocks, k & 1, s));
+    for (int k = 0; k < nsteps; ++k)
+      HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, T.dev, count, blocks, k & 1, s));
   }
   HIPCHK(h0, hipEventRecord(T.done, s));
   bool check = false;

@@ -86,3 +86,23 @@ def test_graph_chunks_equal_direct_launches():
     for a, b in zip(out[False], out[True]):
         for f in a:
             assert np.array_equal(a[f], b[f]), f
+
+
+def test_large_batch_equals_alone():
+    """A batch whose step moves more than the last-level cache (two 128^3
+    FP32 lattices, about 0.8 GB per step) takes the streaming-store path;
+    results are still bitwise those of each lattice alone."""
+    from paper_1507_07294_amd import mplb
+    ws = [wl.static_droplet(n=128, R=30.0, ratio=3.0), wl.static_droplet(n=128, R=22.0, ratio=5.0)]
+    alone = []
+    for w in ws:
+        g = mplb.from_workload(w, "f32")
+        g.step(6)
+        alone.append({k: g.read(k) for k in ("phi", "uz", "p")})
+        g.destroy()
+    mix = [mplb.from_workload(w, "f32") for w in ws]
+    mplb.mplb_step_many(mix, 6)
+    for g, ref in zip(mix, alone):
+        for k, v in ref.items():
+            assert np.array_equal(g.read(k), v), k
+        g.destroy()
