@@ -94,15 +94,14 @@ def cpu_baseline(W, target_s=12.0):
     shape = (w.shape[0], w.shape[1], nz_slab)
     o = orc.Oracle(shape, w.bc, orc.COUPLED, w.params)
     o.init(phi)
-    t0 = time.perf_counter()
-    o.step(1)
-    t1 = time.perf_counter() - t0
-    extra = max(0, min(200, int(target_s / max(t1, 1e-3)) - 1))
-    t0 = time.perf_counter()
-    if extra:
-        o.step(extra)
-    t2 = time.perf_counter() - t0
-    steps = 1 + extra
+    # whole steps until target_s of CPU time has passed (at most 200 steps)
+    steps, elapsed = 0, 0.0
+    while elapsed < target_s and steps < 200:
+        t0 = time.perf_counter()
+        o.step(1)
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    t1, t2 = elapsed, 0.0
     nodes = shape[0] * shape[1] * shape[2]
     mlups = nodes * steps / (t1 + t2) / 1e6
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -193,6 +192,7 @@ def main():
         b = torch.empty_like(a)
         probe = {}
         for name, fn in (("mplb_copy_probe", lambda: mplb.mplb_copy_probe(a, b, nbytes)),
+                         ("mplb_copy_probe_streaming", lambda: mplb.mplb_copy_probe(a, b, nbytes, True)),
                          ("torch_copy", lambda: b.copy_(a))):
             for _ in range(3):
                 fn()

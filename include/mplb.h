@@ -184,8 +184,9 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
 /* Measurement reference: copy `bytes` (a multiple of 16) from device buffer
  * src to device buffer dst with 16-byte loads and stores on hip_stream, so
  * that the bandwidth a plain streaming kernel reaches on this device can be
- * put beside the step's.  Enqueues only. */
-int mplb_copy_probe(const void* src, void* dst, size_t bytes, void* hip_stream);
+ * put beside the step's.  streaming != 0 uses non-temporal stores (the store
+ * policy of the step kernels on large lattices).  Enqueues only. */
+int mplb_copy_probe(const void* src, void* dst, size_t bytes, int streaming, void* hip_stream);
 
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;
  * node n) of the current state with `value`, e.g. to plant a NaN. */

@@ -307,6 +307,14 @@ __global__ void __launch_bounds__(kBlock) k_copy16(const float4* __restrict__ a,
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock) b[i] = a[i];
 }
 
+// the same with non-temporal (streaming) stores, the store policy of the
+// step kernels on large lattices
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(kBlock) k_copy16_nt(const u32x4* __restrict__ a, u32x4* __restrict__ b, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (size_t)gridDim.x * kBlock)
+    __builtin_nontemporal_store(a[i], &b[i]);
+}
+
 __global__ void k_fill_int(int* p, int v, int count) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = v;
@@ -431,8 +439,11 @@ hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, con
   MPLB_DISPATCH(P, return init_impl<PP>(mode, G, C, B, cur, s))
 }
 
-hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, hipStream_t s) {
-  hipLaunchKernelGGL(k_copy16, dim3(32768), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst, bytes / 16);
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int streaming, hipStream_t s) {
+  if (streaming)
+    hipLaunchKernelGGL(k_copy16_nt, dim3(32768), dim3(kBlock), 0, s, (const u32x4*)src, (u32x4*)dst, bytes / 16);
+  else
+    hipLaunchKernelGGL(k_copy16, dim3(32768), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst, bytes / 16);
   return hipGetLastError();
 }
 

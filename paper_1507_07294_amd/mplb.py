@@ -83,7 +83,7 @@ def lib():
             "mplb_restore": (C.c_int, [vp, vp, sz]),
             "mplb_poke": (C.c_int, [vp, C.c_int, C.c_int, C.c_long, C.c_double]),
             "mplb_time_stages": (C.c_int, [vp, C.c_int, dp]),
-            "mplb_copy_probe": (C.c_int, [vp, vp, sz, vp]),
+            "mplb_copy_probe": (C.c_int, [vp, vp, sz, C.c_int, vp]),
             "mplb_destroy": (None, [vp]),
             "mplb_last_error": (C.c_char_p, [vp]),
             "mplb_strerror": (C.c_char_p, [C.c_int]),
@@ -290,12 +290,13 @@ def mplb_set_step_many_graphs(enable):
         raise MplbError(rc, "mplb_set_step_many_graphs")
 
 
-def mplb_copy_probe(src, dst, nbytes, stream=None):
-    """Device copy with 16-byte accesses (bandwidth reference); src, dst are torch tensors."""
+def mplb_copy_probe(src, dst, nbytes, streaming=False, stream=None):
+    """Device copy with 16-byte accesses (bandwidth reference); src, dst are torch tensors;
+    streaming: non-temporal stores."""
     import torch
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     rc = lib().mplb_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), C.c_size_t(nbytes),
-                               C.c_void_p(int(s)))
+                               C.c_int(1 if streaming else 0), C.c_void_p(int(s)))
     if rc:
         raise MplbError(rc, "mplb_copy_probe")
 

@@ -84,6 +84,22 @@ def test_che_only(kind, precision, tol):
     _compare(w, [1, 7, 40], precision, tol, coupled=False)
 
 
+@pytest.mark.parametrize("model", ["mrt", "srt"])
+def test_zalesak_mrt_and_srt(model):
+    """A small slotted sphere under rigid rotation (Eq. 37) with the MRT rates
+    of Eq. 38 and with their SRT special case: GPU FP64 against the oracle,
+    and the Eq. 40 error of both against the initial field."""
+    import dataclasses
+    from paper_1507_07294_amd import interface_study as ist
+    w = wl.zalesak(n=40, R=16.0, slot=6.4, Pe=600.0)
+    if model == "srt":
+        w.params = dataclasses.replace(w.params, s_f=ist.srt_rates(w.params.s_f))
+    o, g = _compare(w, [1, 50, 300], "f64", F64_TOL, coupled=False)
+    eo, eg = ist.err_eq40(o.read("phi"), w.phi0), ist.err_eq40(g.read("phi"), w.phi0)
+    print(f"  Err(Eq. 40) oracle={eo:.6e} gpu={eg:.6e}", flush=True)
+    assert abs(eo - eg) <= 1e-12 * max(eo, 1e-300) + 1e-15
+
+
 def test_che_only_walls_and_ragged():
     """CHE-only with bounce-back on every axis and a box that is not a
     multiple of the tile: phi history, mirror ghosts and walls together."""
