@@ -17,6 +17,7 @@
  *   S5 d_t(phi u) = (phi u)(n) - (phi u)(n-1)                 (Eq. 34)
  *   S6 CHE collision in moment space                          (Eqs. 15, 17, 18, 11)
  *   S7 NSE collision in moment space                          (Eqs. 20, 27, 31, 32)
+ *      (the D3Q19 variant: Gamma_19 g^eq and Gamma_19 T of Eqs. 21, 28)
  *   S8 streaming, periodic wrap or half-way bounce-back       (Eq. 16)
  *
  * Readings of points the paper leaves open (each is listed in the design notes):
@@ -83,10 +84,51 @@ static const double G15_PRINTED[15][15] = {
     {0, 0, 0, 0, 0, 0, 0, 1, -1, 1, -1, -1, 1, -1, 1},
     {0, 0, 0, 0, 0, 0, 0, 1, -1, -1, 1, -1, 1, 1, -1}};
 
+/* D3Q19, the alternative lattice the paper names for the NSE (after Eq. 22):
+ * rest, the six faces in the order of Eq. 23, then the twelve edges in
+ * antipodal pairs.  Weights 1/3, 1/18, 1/36; c_s^2 = 1/3. */
+static const int C19[19][3] = {
+    {0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const double W19[19] = {1.0 / 3,  1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18, 1.0 / 18,
+                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36,
+                               1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+/* D3Q19 moments of d'Humieres et al. (2002): density, energy, energy square,
+ * momentum and heat flux per axis, the five stress components with their
+ * fourth-order partners, and three third-order moments.  Rows 9, 11, 13, 14
+ * and 15 are the stress moments that set the viscosity. */
+static double g19_row(int r, const int c[3]) {
+  const double x = c[0], y = c[1], z = c[2], c2 = x * x + y * y + z * z;
+  switch (r) {
+    case 0: return 1.0;
+    case 1: return 19.0 * c2 - 30.0;
+    case 2: return (21.0 * c2 * c2 - 53.0 * c2 + 24.0) / 2.0;
+    case 3: return x;
+    case 4: return (5.0 * c2 - 9.0) * x;
+    case 5: return y;
+    case 6: return (5.0 * c2 - 9.0) * y;
+    case 7: return z;
+    case 8: return (5.0 * c2 - 9.0) * z;
+    case 9: return 3.0 * x * x - c2;
+    case 10: return (3.0 * c2 - 5.0) * (3.0 * x * x - c2);
+    case 11: return y * y - z * z;
+    case 12: return (3.0 * c2 - 5.0) * (y * y - z * z);
+    case 13: return x * y;
+    case 14: return y * z;
+    case 15: return x * z;
+    case 16: return (y * y - z * z) * x;
+    case 17: return (z * z - x * x) * y;
+    default: return (x * x - y * y) * z;
+  }
+}
+static const int VISC19[5] = {9, 11, 13, 14, 15};
+
 static double G15[15][15];     /* Gamma in the Eq. 23 velocity order */
 static double G15_INV[15][15]; /* Gamma^-1 = Gamma^T diag(1/(Gamma Gamma^T)_ii) */
 static double M7_INV[7][7];
-static int OPP7[7], OPP15[15];
+static double G19[19][19], G19_INV[19][19];
+static int OPP7[7], OPP15[15], OPP19[19];
 static int tables_ready = 0;
 
 /* Builds Gamma in the Eq. 23 order, the inverses and the opposite-direction
@@ -129,6 +171,22 @@ static void build_tables(void) {
     for (int j = 0; j < 15; ++j)
       if (C15[j][0] == -C15[i][0] && C15[j][1] == -C15[i][1] && C15[j][2] == -C15[i][2])
         OPP15[i] = j;
+  for (int r = 0; r < 19; ++r)
+    for (int i = 0; i < 19; ++i) G19[r][i] = g19_row(r, C19[i]);
+  for (int r = 0; r < 19; ++r) {
+    double d = 0;
+    for (int i = 0; i < 19; ++i) d += G19[r][i] * G19[r][i];
+    for (int r2 = 0; r2 < 19; ++r2) {
+      double o = 0;
+      for (int i = 0; i < 19; ++i) o += G19[r][i] * G19[r2][i];
+      if (r2 != r && o != 0.0) abort();
+    }
+    for (int i = 0; i < 19; ++i) G19_INV[i][r] = G19[r][i] / d;
+  }
+  for (int i = 0; i < 19; ++i)
+    for (int j = 0; j < 19; ++j)
+      if (C19[j][0] == -C19[i][0] && C19[j][1] == -C19[i][1] && C19[j][2] == -C19[i][2])
+        OPP19[i] = j;
   tables_ready = 1;
 }
 
@@ -142,12 +200,16 @@ static void weights7(double A, double w[7]) {
 
 struct orc_s {
   int n[3], bc[3], mode;
+  int q;                  /* NSE lattice: 15 (Eq. 23) or 19 */
+  const int (*cg)[3];     /* its velocities, weights and opposite directions */
+  const double* wg;
+  const int* oppg;
   long N;
   int have_params, have_init;
   orc_params p;
   /* derived parameters */
   double beta, kappa, tau_f, eta, tau_g, drho;
-  double sf[7], lg[15];
+  double sf[7], lg[19];
   /* state at level n */
   double *f, *g, *phiu;
   long step;
@@ -178,7 +240,7 @@ static long stencil_nb(const orc_t* s, int x, int y, int z, int dx, int dy, int 
 orc_t* orc_create(int nx, int ny, int nz, const int bc[3], int mode) {
   build_tables();
   if (nx < 1 || ny < 1 || nz < 1 || !bc) return NULL;
-  if (mode != ORC_COUPLED && mode != ORC_CHE_ONLY) return NULL;
+  if (mode != ORC_COUPLED && mode != ORC_CHE_ONLY && mode != ORC_COUPLED_Q19) return NULL;
   for (int a = 0; a < 3; ++a)
     if (bc[a] != ORC_PERIODIC && bc[a] != ORC_WALL) return NULL;
   orc_t* s = (orc_t*)calloc(1, sizeof(orc_t));
@@ -186,13 +248,17 @@ orc_t* orc_create(int nx, int ny, int nz, const int bc[3], int mode) {
   s->n[0] = nx; s->n[1] = ny; s->n[2] = nz;
   for (int a = 0; a < 3; ++a) s->bc[a] = bc[a];
   s->mode = mode;
+  s->q = (mode == ORC_COUPLED_Q19) ? 19 : 15;
+  s->cg = (s->q == 19) ? C19 : C15;
+  s->wg = (s->q == 19) ? W19 : W15;
+  s->oppg = (s->q == 19) ? OPP19 : OPP15;
   s->N = (long)nx * ny * nz;
   long N = s->N;
   s->f = calloc(7 * N, sizeof(double));
-  s->g = calloc(15 * N, sizeof(double));
+  s->g = calloc(s->q * N, sizeof(double));
   s->phiu = calloc(3 * N, sizeof(double));
   s->fpost = calloc(7 * N, sizeof(double));
-  s->gpost = calloc(15 * N, sizeof(double));
+  s->gpost = calloc(s->q * N, sizeof(double));
   s->phi = calloc(N, sizeof(double));
   s->rho = calloc(N, sizeof(double));
   s->mu = calloc(N, sizeof(double));
@@ -246,9 +312,16 @@ int orc_set_params(orc_t* s, const orc_params* p) {
   s->beta = d[0]; s->kappa = d[1]; s->tau_f = d[2]; s->eta = d[3]; s->tau_g = d[4];
   s->drho = p->rho_l - p->rho_g;
   for (int i = 0; i < 7; ++i) s->sf[i] = p->s_f[i];
-  for (int i = 0; i < 15; ++i) s->lg[i] = p->lambda_g[i];
-  for (int i = 9; i <= 13; ++i) s->lg[i] = d[5];
-  for (int i = 0; i < 15; ++i)
+  if (s->q == 19) {
+    /* D3Q19: the stress moments relax at 1/tau_g (Eq. 33), the others at 1
+     * (the paper's choice for S^g, Sec. III C) */
+    for (int r = 0; r < 19; ++r) s->lg[r] = 1.0;
+    for (int k = 0; k < 5; ++k) s->lg[VISC19[k]] = d[5];
+  } else {
+    for (int i = 0; i < 15; ++i) s->lg[i] = p->lambda_g[i];
+    for (int i = 9; i <= 13; ++i) s->lg[i] = d[5];
+  }
+  for (int i = 0; i < s->q; ++i)
     if (!(s->lg[i] > 0 && s->lg[i] < 2)) { snprintf(s->err, sizeof s->err, "lambda out of (0,2)"); return ORC_E_INVAL; }
   s->have_params = 1;
   return ORC_OK;
@@ -292,6 +365,53 @@ static double s_of_u(int i, const double u[3]) {
   double cu = C_LAT * (C15[i][0] * u[0] + C15[i][1] * u[1] + C15[i][2] * u[2]);
   double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
   return W15[i] * (cu / CS2_G + cu * cu / (2.0 * CS2_G * CS2_G) - uu / (2.0 * CS2_G));
+}
+
+/* s_i(u), Eq. 22, for velocity c with weight w */
+static double s_of_cw(const int c[3], double w, const double u[3]) {
+  double cu = C_LAT * (c[0] * u[0] + c[1] * u[1] + c[2] * u[2]);
+  double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  return w * (cu / CS2_G + cu * cu / (2.0 * CS2_G * CS2_G) - uu / (2.0 * CS2_G));
+}
+
+/* Eq. 21 on a lattice of q velocities c with weights w */
+static void geq_qw(int q, const int (*c)[3], const double* w, double p, double rho, const double u[3],
+                   double* geq) {
+  for (int i = 0; i < q; ++i) geq[i] = p / CS2_G * (i == 0 ? w[0] - 1.0 : w[i]) + rho * s_of_cw(c[i], w[i], u);
+}
+
+/* Eq. 28 on a lattice of q velocities: T_i = (c_i - u)/c_s^2 . [s_i(u)
+ * grad(rho c_s^2) + F (s_i(u) + w_i)], with F = F_s + F_a + G */
+static void T_qw(int q, const int (*c)[3], const double* w, const double u[3], const double gr[3],
+                 const double F[3], double* T) {
+  for (int i = 0; i < q; ++i) {
+    double si = s_of_cw(c[i], w[i], u), acc = 0.0;
+    for (int a = 0; a < 3; ++a) acc += (C_LAT * c[i][a] - u[a]) * (si * gr[a] * CS2_G + F[a] * (si + w[i]));
+    T[i] = acc / CS2_G;
+  }
+}
+
+static void geq_of(const orc_t* s, double p, double rho, const double u[3], double* geq) {
+  geq_qw(s->q, s->cg, s->wg, p, rho, u, geq);
+}
+static void T_of(const orc_t* s, const double u[3], const double gr[3], const double F[3], double* T) {
+  T_qw(s->q, s->cg, s->wg, u, gr, F, T);
+}
+
+void orc_lattice19(int* c19, double* w19, double* G) {
+  build_tables();
+  for (int i = 0; i < 19; ++i) {
+    if (c19) for (int a = 0; a < 3; ++a) c19[i * 3 + a] = C19[i][a];
+    if (w19) w19[i] = W19[i];
+  }
+  if (G) for (int r = 0; r < 19; ++r) for (int i = 0; i < 19; ++i) G[r * 19 + i] = G19[r][i];
+}
+
+void orc_geq19(double p, double rho, const double u[3], double geq[19]) { geq_qw(19, C19, W19, p, rho, u, geq); }
+
+void orc_T(int q, const double u[3], const double gr[3], const double F[3], double* T) {
+  if (q == 19) T_qw(19, C19, W19, u, gr, F, T);
+  else T_qw(15, C15, W15, u, gr, F, T);
 }
 
 /* Eq. 21 */
@@ -494,9 +614,9 @@ static void compute_macro(orc_t* s) {
           Fs[a] = mu * gphi[a];                            /* F_s = mu grad phi (after Eq. 28) */
           G[a] = (rho - s->p.rho_ref) * s->p.gravity[a]; /* external force */
         }
-        for (int i = 0; i < 15; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           double gi = s->g[i * N + n];
-          for (int a = 0; a < 3; ++a) j[a] += C_LAT * C15[i][a] * gi;
+          for (int a = 0; a < 3; ++a) j[a] += C_LAT * s->cg[i][a] * gi;
           if (i != 0) sum_nz += gi;
         }
         /* Eq. 29 */
@@ -506,7 +626,7 @@ static void compute_macro(orc_t* s) {
         for (int a = 0; a < 3; ++a) F[a] = Fs[a] + 0.5 * s->drho * s->p.mobility * lapmu * u[a] + G[a];
         /* Eq. 30 */
         double ugr = u[0] * gr[0] + u[1] * gr[1] + u[2] * gr[2];
-        s->pr[n] = CS2_G / (1.0 - W15[0]) * (sum_nz + 0.5 * ugr + rho * s_of_u(0, u));
+        s->pr[n] = CS2_G / (1.0 - s->wg[0]) * (sum_nz + 0.5 * ugr + rho * s_of_cw(s->cg[0], s->wg[0], u));
         for (int a = 0; a < 3; ++a) {
           s->u[a * N + n] = u[a];
           s->F[a * N + n] = F[a];
@@ -523,7 +643,7 @@ static int check_finite(orc_t* s) {
 #pragma omp parallel for reduction(| : bad)
   for (long k = 0; k < 7 * N; ++k) bad |= !isfinite(s->f[k]);
 #pragma omp parallel for reduction(| : bad)
-  for (long k = 0; k < 15 * N; ++k) bad |= !isfinite(s->g[k]);
+  for (long k = 0; k < s->q * N; ++k) bad |= !isfinite(s->g[k]);
   return bad;
 }
 
@@ -557,11 +677,33 @@ static void step_once(orc_t* s) {
     }
     if (s->mode == ORC_CHE_ONLY) continue;
     /* S7: m = Gamma g; m* = m - S^g (m - m^eq) + (I - S^g/2) mT; g* = Gamma^-1 m*  (Eqs. 20, 27, 31, 32) */
-    double gl[15], mg[15], mgeq[15], mT[15], mgs[15], gr[3], F[3];
-    for (int i = 0; i < 15; ++i) gl[i] = s->g[i * N + n];
+    double gl[19], mg[19], mgeq[19], mT[19], mgs[19], gr[3], F[3];
+    for (int i = 0; i < s->q; ++i) gl[i] = s->g[i * N + n];
     for (int a = 0; a < 3; ++a) {
       gr[a] = s->gradrho[a * N + n];
       F[a] = s->F[a * N + n];
+    }
+    if (s->q == 19) {
+      /* D3Q19: m = Gamma_19 g, m^eq = Gamma_19 g^eq (Eq. 21), m_T = Gamma_19 T
+       * (Eq. 28); m* = m - S(m - m^eq) + (I - S/2) m_T; g* = Gamma_19^-1 m* */
+      double geq[19], T[19];
+      geq_of(s, s->pr[n], s->rho[n], u, geq);
+      T_of(s, u, gr, F, T);
+      for (int r = 0; r < 19; ++r) {
+        mg[r] = mgeq[r] = mT[r] = 0.0;
+        for (int i = 0; i < 19; ++i) {
+          mg[r] += G19[r][i] * gl[i];
+          mgeq[r] += G19[r][i] * geq[i];
+          mT[r] += G19[r][i] * T[i];
+        }
+        mgs[r] = mg[r] - s->lg[r] * (mg[r] - mgeq[r]) + (1.0 - s->lg[r] / 2.0) * mT[r];
+      }
+      for (int i = 0; i < 19; ++i) {
+        double v = 0.0;
+        for (int r = 0; r < 19; ++r) v += G19_INV[i][r] * mgs[r];
+        s->gpost[i * N + n] = v;
+      }
+      continue;
     }
     for (int r = 0; r < 15; ++r) {
       mg[r] = 0.0;
@@ -598,16 +740,16 @@ static void step_once(orc_t* s) {
           else s->f[i * N + idx(s, q[0], q[1], q[2])] = s->fpost[i * N + n];
         }
         if (s->mode == ORC_CHE_ONLY) continue;
-        for (int i = 0; i < 15; ++i) {
+        for (int i = 0; i < s->q; ++i) {
           int wall = 0;
           for (int a = 0; a < 3; ++a) {
-            q[a] = p[a] + C15[i][a];
+            q[a] = p[a] + s->cg[i][a];
             if (q[a] < 0 || q[a] >= s->n[a]) {
               if (s->bc[a] == ORC_WALL) wall = 1;
               else q[a] = (q[a] + s->n[a]) % s->n[a];
             }
           }
-          if (wall) s->g[OPP15[i] * N + n] = s->gpost[i * N + n];
+          if (wall) s->g[s->oppg[i] * N + n] = s->gpost[i * N + n];
           else s->g[i * N + idx(s, q[0], q[1], q[2])] = s->gpost[i * N + n];
         }
       }
@@ -655,11 +797,11 @@ int orc_init(orc_t* s, const double* phi0, const double* u0) {
         if (s->mode == ORC_CHE_ONLY) prescribed_u(s, x, y, z, 0, u);
         else if (u0) for (int a = 0; a < 3; ++a) u[a] = u0[a * N + n];
         double rho = (1.0 + phi) / 2.0 * s->p.rho_l + (1.0 - phi) / 2.0 * s->p.rho_g;
-        double feq[7], geq[15];
+        double feq[7], geq[19];
         orc_feq(s->p.A, s->eta, phi, mu, u, feq); /* Eq. 5 */
         for (int i = 0; i < 7; ++i) s->f[i * N + n] = feq[i];
-        orc_geq(0.0, rho, u, geq); /* Eq. 21 with p = 0 */
-        for (int i = 0; i < 15; ++i) s->g[i * N + n] = (s->mode == ORC_CHE_ONLY) ? 0.0 : geq[i];
+        geq_of(s, 0.0, rho, u, geq); /* Eq. 21 with p = 0 */
+        for (int i = 0; i < s->q; ++i) s->g[i * N + n] = (s->mode == ORC_CHE_ONLY) ? 0.0 : geq[i];
         for (int a = 0; a < 3; ++a) s->phiu[a * N + n] = phi * u[a];
       }
   free(lap);
@@ -695,8 +837,8 @@ int orc_totals(orc_t* s, double out[7]) {
   for (long n = 0; n < N; ++n) out[0] += s->phi[n];
   if (s->mode == ORC_CHE_ONLY) return ORC_OK;
   for (long n = 0; n < N; ++n)
-    for (int i = 0; i < 15; ++i)
-      for (int a = 0; a < 3; ++a) out[1 + a] += C_LAT * C15[i][a] * s->g[i * N + n];
+    for (int i = 0; i < s->q; ++i)
+      for (int a = 0; a < 3; ++a) out[1 + a] += C_LAT * s->cg[i][a] * s->g[i * N + n];
   for (int a = 0; a < 3; ++a)
     for (long n = 0; n < N; ++n) out[4 + a] += s->F[a * N + n];
   return ORC_OK;
@@ -727,7 +869,7 @@ int orc_front(orc_t* s, double out[2]) {
 int orc_get_state(const orc_t* s, double* f, double* g, double* phiu) {
   if (!s) return ORC_E_INVAL;
   if (f) memcpy(f, s->f, 7 * s->N * sizeof(double));
-  if (g) memcpy(g, s->g, 15 * s->N * sizeof(double));
+  if (g) memcpy(g, s->g, s->q * s->N * sizeof(double));
   if (phiu) memcpy(phiu, s->phiu, 3 * s->N * sizeof(double));
   return ORC_OK;
 }
@@ -735,7 +877,7 @@ int orc_get_state(const orc_t* s, double* f, double* g, double* phiu) {
 int orc_set_state(orc_t* s, const double* f, const double* g, const double* phiu) {
   if (!s) return ORC_E_INVAL;
   if (f) memcpy(s->f, f, 7 * s->N * sizeof(double));
-  if (g) memcpy(s->g, g, 15 * s->N * sizeof(double));
+  if (g) memcpy(s->g, g, s->q * s->N * sizeof(double));
   if (phiu) memcpy(s->phiu, phiu, 3 * s->N * sizeof(double));
   return ORC_OK;
 }

@@ -24,7 +24,14 @@ extern "C" {
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 2, ORC_E_STATE = 4, ORC_E_NONFINITE = 5 };
 enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
-enum { ORC_COUPLED = 0, ORC_CHE_ONLY = 1 };
+/* ORC_COUPLED: D3Q7 CHE + D3Q15 NSE (the paper's model); ORC_CHE_ONLY: the
+ * interface-tracking runs; ORC_COUPLED_Q19: the NSE on D3Q19, the other
+ * lattice the paper names (after Eq. 22): velocities rest, 6 faces (Eq. 23
+ * order), 12 edges in antipodal pairs; weights 1/3, 1/18, 1/36; moments of
+ * d'Humieres et al. (2002); g^eq (Eq. 21) and T (Eq. 28) transformed exactly
+ * (no truncated form of Eq. 32 exists for it); the five stress moments
+ * relax at 1/tau_g (Eq. 33), all others at 1, and lambda_g is not used. */
+enum { ORC_COUPLED = 0, ORC_CHE_ONLY = 1, ORC_COUPLED_Q19 = 2 };
 enum { ORC_PHI = 0, ORC_RHO = 1, ORC_MU = 2, ORC_UX = 3, ORC_UY = 4, ORC_UZ = 5, ORC_P = 6 };
 /* prescribed velocity for the interface-tracking runs (Sec. III A-B) */
 enum { ORC_VEL_ZERO = 0, ORC_VEL_FIELD = 1, ORC_VEL_ZALESAK = 2, ORC_VEL_DEFORM = 3 };
@@ -67,7 +74,15 @@ int orc_totals(orc_t* s, double out[7]);
  * phi = 0 counts as positive); -1, -1 when no column crosses.  Layers are
  * scanned 0..nz-1 without wrapping. */
 int orc_front(orc_t* s, double out[2]);
-/* Populations at the current level (after streaming): f[7N], g[15N], phiu[3N]
+/* D3Q19 tables: velocities c19[19*3], weights w19[19], moment matrix
+ * G[19*19] (row-major; any pointer may be NULL). */
+void orc_lattice19(int* c19, double* w19, double* G);
+/* Eq. 21 on D3Q19 */
+void orc_geq19(double p, double rho, const double u[3], double geq[19]);
+/* Eq. 28 on D3Q15 (q = 15, the Eq. 23 order) or D3Q19 (q = 19):
+ * T[q] for velocity u, grad rho gr and force F = F_s + F_a + G. */
+void orc_T(int q, const double u[3], const double gr[3], const double F[3], double* T);
+/* Populations at the current level (after streaming): f[7N], g[15N] (g[19N] for ORC_COUPLED_Q19), phiu[3N]
  * holds (phi u) of the previous level.  Any pointer may be NULL. */
 int orc_get_state(const orc_t* s, double* f, double* g, double* phiu);
 int orc_set_state(orc_t* s, const double* f, const double* g, const double* phiu);

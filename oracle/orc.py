@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY.  Argument marshalling; no arithmetic of the method.
 Arrays use the lattice layout of the C code: a scalar field is a float64 array
 of shape (nz, ny, nx) (x fastest); a vector field is (3, nz, ny, nx); the
-populations are (7, nz, ny, nx) and (15, nz, ny, nx).
+populations are (7, nz, ny, nx) and (15, nz, ny, nx) ((19, ...) for COUPLED_Q19).
 """
 from __future__ import annotations
 
@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("ORC_LIB_PATH") or os.path.join(_HERE, "liborc.so")
 
 PERIODIC, WALL = 0, 1
-COUPLED, CHE_ONLY = 0, 1
+COUPLED, CHE_ONLY, COUPLED_Q19 = 0, 1, 2
 FIELDS = {"phi": 0, "rho": 1, "mu": 2, "ux": 3, "uy": 4, "uz": 5, "p": 6}
 VEL_ZERO, VEL_FIELD, VEL_ZALESAK, VEL_DEFORM = 0, 1, 2, 3
 E_NONFINITE = 5
@@ -61,6 +61,9 @@ def lib():
         L.orc_step_count.argtypes = [C.c_void_p]
         L.orc_read.argtypes = [C.c_void_p, C.c_int, dp]
         L.orc_totals.argtypes = [C.c_void_p, dp]
+        L.orc_lattice19.argtypes = [ip, dp, dp]
+        L.orc_geq19.argtypes = [C.c_double, C.c_double, dp, dp]
+        L.orc_T.argtypes = [C.c_int, dp, dp, dp, dp]
         L.orc_front.argtypes = [C.c_void_p, dp]
         L.orc_get_state.argtypes = [C.c_void_p, dp, dp, dp]
         L.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp]
@@ -182,7 +185,7 @@ class Oracle:
 
     def get_state(self):
         f = np.empty((7,) + self.grid)
-        g = np.empty((15,) + self.grid)
+        g = np.empty((19 if self.mode == COUPLED_Q19 else 15,) + self.grid)
         pu = np.empty((3,) + self.grid)
         self._chk(lib().orc_get_state(self._h, _dp(f), _dp(g), _dp(pu)))
         return f, g, pu
@@ -261,4 +264,26 @@ def meq_g(p, rho, u):
 def mT(u, grad_rho, F):
     out = np.empty(15)
     lib().orc_mT(_dp(_f64(u)), _dp(_f64(grad_rho)), _dp(_f64(F)), _dp(out))
+    return out
+
+
+def lattice19():
+    """(c19 (19, 3), w19 (19,), Gamma_19 (19, 19)) of the D3Q19 variant."""
+    c = np.empty((19, 3), dtype=np.int32)
+    w = np.empty(19)
+    G = np.empty((19, 19))
+    lib().orc_lattice19(c.ctypes.data_as(C.POINTER(C.c_int)), _dp(w), _dp(G))
+    return c, w, G
+
+
+def geq19(p, rho, u):
+    out = np.empty(19)
+    lib().orc_geq19(float(p), float(rho), _dp(_f64(u)), _dp(out))
+    return out
+
+
+def T(q, u, grad_rho, F):
+    """Eq. 28 on D3Q15 (q = 15) or D3Q19 (q = 19)."""
+    out = np.empty(q)
+    lib().orc_T(int(q), _dp(_f64(u)), _dp(_f64(grad_rho)), _dp(_f64(F)), _dp(out))
     return out

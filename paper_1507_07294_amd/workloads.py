@@ -58,6 +58,7 @@ class Workload:
     u0: Optional[np.ndarray] = None
     steps: int = 0
     velocity: Optional[dict] = None  # prescribed flow for the interface-tracking runs
+    nse_q: int = 15  # lattice of the Navier-Stokes populations: 15 (the paper's) or 19
 
     @property
     def nodes(self) -> int:

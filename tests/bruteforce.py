@@ -45,6 +45,26 @@ def weights15():
     return np.array([2 / 9] + [1 / 9] * 6 + [1 / 72] * 8)
 
 
+def velocities19():
+    return load_matrix("d3q19_velocities.txt").T.astype(int)  # (19, 3)
+
+
+def weights19():
+    return np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+
+
+def gamma19_polynomial(c):
+    """d'Humieres et al. (2002) D3Q19 basis on velocities c."""
+    cx, cy, cz = c[:, 0].astype(float), c[:, 1].astype(float), c[:, 2].astype(float)
+    c2 = cx * cx + cy * cy + cz * cz
+    rows = [np.ones_like(cx), 19 * c2 - 30, (21 * c2 * c2 - 53 * c2 + 24) / 2,
+            cx, (5 * c2 - 9) * cx, cy, (5 * c2 - 9) * cy, cz, (5 * c2 - 9) * cz,
+            3 * cx * cx - c2, (3 * c2 - 5) * (3 * cx * cx - c2), cy * cy - cz * cz,
+            (3 * c2 - 5) * (cy * cy - cz * cz), cx * cy, cy * cz, cx * cz,
+            (cy * cy - cz * cz) * cx, (cz * cz - cx * cx) * cy, (cx * cx - cy * cy) * cz]
+    return np.array(rows)
+
+
 def matrix_M():
     return load_matrix("eq09_M_d3q7.txt")
 
@@ -64,7 +84,7 @@ def opposite(c):
 
 
 class Brute:
-    def __init__(self, shape, bc, params, coupled=True, u_field=None):
+    def __init__(self, shape, bc, params, coupled=True, u_field=None, q=15):
         self.nx, self.ny, self.nz = shape
         self.bc = bc
         self.p = params
@@ -73,21 +93,28 @@ class Brute:
         A = params.A
         self.c7, self.w7, self.cs2f = velocities7(), weights7(A), A
         self.c15, self.w15, self.cs2 = velocities15(), weights15(), 1.0 / 3.0
+        self.q = q
+        # lattice of the g populations (the stencils keep the D3Q15 weights)
+        self.cg, self.wg = (velocities19(), weights19()) if q == 19 else (self.c15, self.w15)
         self.M = matrix_M()
-        self.Gm = gamma_polynomial(self.c15)
+        self.Gm = gamma19_polynomial(self.cg) if q == 19 else gamma_polynomial(self.c15)
         self.Minv = np.linalg.inv(self.M)
         self.Ginv = np.linalg.inv(self.Gm)
-        self.opp7, self.opp15 = opposite(self.c7), opposite(self.c15)
+        self.opp7, self.opp15 = opposite(self.c7), opposite(self.cg)
         self.beta = 3 * params.sigma / (4 * params.width)
         self.kappa = 3 * params.width * params.sigma / 8
         tau_f = 1 / params.s_f[1]
         self.eta = params.mobility / (A * (tau_f - 0.5))
         tau_g = 3 * params.nu + 0.5
-        lam = np.array(params.lambda_g, dtype=float)
-        lam[9:14] = 1 / tau_g
+        if q == 19:  # stress moments at 1/tau_g, the rest at 1
+            lam = np.ones(19)
+            lam[[9, 11, 13, 14, 15]] = 1 / tau_g
+        else:
+            lam = np.array(params.lambda_g, dtype=float)
+            lam[9:14] = 1 / tau_g
         self.Sf = np.diag(params.s_f)
         self.Sg = np.diag(lam)
-        I7, I15 = np.eye(7), np.eye(15)
+        I7, I15 = np.eye(7), np.eye(q)
         self.Kf = self.Minv @ self.Sf @ self.M
         self.Rf = self.Minv @ (I7 - self.Sf / 2) @ self.M
         self.Kg = self.Ginv @ self.Sg @ self.Gm
@@ -138,13 +165,13 @@ class Brute:
         lmu = self.lap(mu)
         Fs = mu * gphi
         G = np.stack([(rho - p.rho_ref) * p.gravity[a] for a in range(3)])
-        j = np.einsum("ia,i...->a...", self.c15.astype(float), g)
+        j = np.einsum("ia,i...->a...", self.cg.astype(float), g)
         dr = p.rho_l - p.rho_g
         u = (j + 0.5 * (Fs + G)) / (rho - 0.25 * dr * p.mobility * lmu)
         F = Fs + 0.5 * dr * p.mobility * lmu * u + G
         uu = (u ** 2).sum(axis=0)
-        s0 = self.w15[0] * (-uu / (2 * self.cs2))
-        pr = self.cs2 / (1 - self.w15[0]) * (g[1:].sum(axis=0) + 0.5 * (u * grho).sum(axis=0) + rho * s0)
+        s0 = self.wg[0] * (-uu / (2 * self.cs2))
+        pr = self.cs2 / (1 - self.wg[0]) * (g[1:].sum(axis=0) + 0.5 * (u * grho).sum(axis=0) + rho * s0)
         return dict(phi=phi, rho=rho, mu=mu, u=u, p=pr, F=F, grho=grho)
 
     def feq(self, phi, mu, u):
@@ -161,14 +188,30 @@ class Brute:
             out[i] = self.w7[i] * sum(self.c7[i][a] * dphiu[a] for a in range(3)) / self.cs2f
         return out
 
-    def geq(self, pr, rho, u):
-        out = np.empty((15,) + pr.shape)
+    def s_i(self, u):
+        """s_i(u) of Eq. 22 for every velocity of the g lattice."""
         uu = (u ** 2).sum(axis=0)
-        for i in range(15):
-            cu = sum(self.c15[i][a] * u[a] for a in range(3))
-            s = self.w15[i] * (cu / self.cs2 + cu ** 2 / (2 * self.cs2 ** 2) - uu / (2 * self.cs2))
-            out[i] = pr / self.cs2 * (self.w15[i] - (1.0 if i == 0 else 0.0)) + rho * s
+        out = np.empty((self.q,) + uu.shape)
+        for i in range(self.q):
+            cu = sum(self.cg[i][a] * u[a] for a in range(3))
+            out[i] = self.wg[i] * (cu / self.cs2 + cu ** 2 / (2 * self.cs2 ** 2) - uu / (2 * self.cs2))
         return out
+
+    def geq(self, pr, rho, u):
+        s = self.s_i(u)
+        out = np.empty((self.q,) + pr.shape)
+        for i in range(self.q):
+            out[i] = pr / self.cs2 * (self.wg[i] - (1.0 if i == 0 else 0.0)) + rho * s[i]
+        return out
+
+    def T(self, u, grho, F):
+        """Eq. 28 in velocity space."""
+        s = self.s_i(u)
+        out = np.zeros((self.q,) + u.shape[1:])
+        for i in range(self.q):
+            for a in range(3):
+                out[i] += (self.cg[i][a] - u[a]) * (s[i] * grho[a] * self.cs2 + F[a] * (s[i] + self.wg[i]))
+        return out / self.cs2
 
     def mT(self, u, grho, F):
         """Eq. 32 (c = 1)."""
@@ -209,9 +252,12 @@ class Brute:
         if not self.coupled:
             return f_new, g, phiu
         ge = self.geq(m["p"], m["rho"], m["u"])
-        mt = self.mT(m["u"], m["grho"], m["F"])
+        if self.q == 19:  # no printed moment form: Gamma T of Eq. 28
+            mt = np.einsum("ij,j...->i...", self.Gm, self.T(m["u"], m["grho"], m["F"]))
+        else:
+            mt = self.mT(m["u"], m["grho"], m["F"])
         gpost = g - np.einsum("ij,j...->i...", self.Kg, g - ge) + np.einsum("ij,j...->i...", self.Hg, mt)
-        g_new = self._stream(gpost, self.c15, self.opp15)
+        g_new = self._stream(gpost, self.cg, self.opp15)
         return f_new, g_new, phiu
 
     def init(self, phi0, u0=None):
@@ -222,5 +268,5 @@ class Brute:
         mu = 4 * self.beta * phi0 * (phi0 ** 2 - 1) - self.kappa * self.lap(phi0)
         rho = (1 + phi0) / 2 * self.p.rho_l + (1 - phi0) / 2 * self.p.rho_g
         f = self.feq(phi0, mu, u)
-        g = self.geq(np.zeros_like(phi0), rho, u) if self.coupled else np.zeros((15,) + phi0.shape)
+        g = self.geq(np.zeros_like(phi0), rho, u) if self.coupled else np.zeros((self.q,) + phi0.shape)
         return f, g, phi0 * u

@@ -11,7 +11,8 @@ FIELDS = ("phi", "rho", "mu", "ux", "uy", "uz", "p")
 
 
 def oracle_for(w):
-    o = orc.Oracle(w.shape, w.bc, orc.COUPLED if w.coupled else orc.CHE_ONLY, w.params)
+    mode = (orc.COUPLED_Q19 if w.nse_q == 19 else orc.COUPLED) if w.coupled else orc.CHE_ONLY
+    o = orc.Oracle(w.shape, w.bc, mode, w.params)
     if not w.coupled:
         v = w.velocity or {"kind": "zero"}
         kind = {"zero": orc.VEL_ZERO, "field": orc.VEL_FIELD, "zalesak": orc.VEL_ZALESAK,
