@@ -26,6 +26,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per lattice update (22 populations + 3-word (phi u)
 # history, each read and written once), per storage mode
 ALGO_BYTES = {"f64": 400, "f32": 200, "f16": 116, "bf16": 116}
+Q19_ALGO_BYTES = {"f64": 464, "f32": 232}  # D3Q19: 19 g instead of 15
 CHE_ALGO_BYTES = {"f64": 2 * 8 * 8, "f32": 2 * 4 * 8}  # 7 populations + phi of the previous level
 
 
@@ -37,6 +38,7 @@ def parse():
     ap.add_argument("--W", type=int, default=256, help="Rayleigh-Taylor box width (box W x W x 4W)")
     ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage precisions to time ('' for none)")
     ap.add_argument("--no-che", action="store_true", help="skip the CHE-only interface-tracking line")
+    ap.add_argument("--no-q19", action="store_true", help="skip the D3Q19 variant of the NSE lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
     ap.add_argument("--serving-requests", type=int, default=48,
@@ -169,6 +171,21 @@ def main():
         torch.cuda.empty_cache()
     if variants:
         result["variants"] = variants
+
+    if not args.no_q19:
+        print(f"[bench] {wname} f32 D3Q19", file=sys.stderr, flush=True)
+        w.nse_q = 19
+        lt = mplb.from_workload(w, "f32")
+        w.nse_q = 15
+        steps = max(10, args.steps // 2)
+        dtq, stq = time_lattice(lt, steps, max(2, args.warmup // 2))
+        result["d3q19"] = {"MLUPS": round(N * steps / dtq / 1e6, 1), "ms_per_step": round(dtq / steps * 1e3, 4),
+                           "algorithmic_bytes_per_lup": Q19_ALGO_BYTES["f32"],
+                           "hbm_frac_step": round(Q19_ALGO_BYTES["f32"] * N / (dtq / steps) / 1e9 / HBM_PEAK_GBPS, 4),
+                           "k_step_ms": round(stq[2], 4)}
+        lt.destroy()
+        del lt
+        torch.cuda.empty_cache()
 
     if not args.no_che:
         wc = wl.deformation_flow(n=128)

@@ -54,6 +54,16 @@ extern "C" {
 /* what a step advances */
 #define MPLB_COUPLED 0  /* Eqs. 4 and 20 (Sec. II) */
 #define MPLB_CHE_ONLY 1 /* Eq. 4 under a prescribed velocity (Sec. III A-B) */
+/* Eqs. 4 and 20 with the NSE populations on D3Q19, the other lattice the
+ * paper names (Sec. II B, after Eq. 22): rest, the six faces in the order of
+ * Eq. 23, then the twelve edges in antipodal pairs ((1,1,0), (-1,-1,0),
+ * (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1), (1,0,-1), (-1,0,1), (0,1,1),
+ * (0,-1,-1), (0,1,-1), (0,-1,1)); weights 1/3, 1/18, 1/36.  The collision
+ * relaxes the five stress moments of d'Humieres' D3Q19 basis at 1/tau_g
+ * (Eq. 33) and every other moment at 1 (lambda_g is not used); g^eq and the
+ * source are Eqs. 21 and 28 taken exactly.  FP64 and FP32 storage only;
+ * mplb_step_many steps such lattices one after another. */
+#define MPLB_COUPLED_Q19 2
 
 /* fields for mplb_read */
 #define MPLB_PHI 0 /* order parameter, Eq. 13 */
@@ -88,7 +98,8 @@ typedef struct mplb_s mplb_t;
 
 /* Device bytes a lattice needs (populations of two time levels, the
  * (phi u) history (3 words per node; CHE-only: phi, 1 word), phi, mu, a
- * read-out buffer and reduction scratch). */
+ * read-out buffer and reduction scratch).  MPLB_E_INVAL for a mode and
+ * precision that do not go together (MPLB_COUPLED_Q19 with 16-bit storage). */
 int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes);
 
 /* Create a lattice of nx*ny*nz nodes (each >= 1) with bc[a] in

@@ -23,7 +23,18 @@ __host__ __device__ constexpr int c7(int i, int a) {
   constexpr int t[7][3] = {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1}};
   return t[i][a];
 }
-// both lattices list velocities in antipodal pairs (1,2), (3,4), ...
+// D3Q19 (the other NSE lattice the paper names, after Eq. 22): rest, the
+// faces in the order of Eq. 23, then the twelve edges
+__host__ __device__ constexpr int c19(int i, int a) {
+  constexpr int t[19][3] = {{0, 0, 0},  {1, 0, 0},  {-1, 0, 0}, {0, 1, 0},   {0, -1, 0}, {0, 0, 1},  {0, 0, -1},
+                            {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+                            {-1, 0, 1}, {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  return t[i][a];
+}
+// velocity i of the NSE lattice with Q velocities (15 or 19)
+template <int Q>
+__host__ __device__ constexpr int cq(int i, int a) { return Q == 19 ? c19(i, a) : c15(i, a); }
+// all lattices list velocities in antipodal pairs (1,2), (3,4), ...
 __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
 
 // ---------------------------------------------------------------- storage
@@ -121,12 +132,12 @@ __device__ inline void pull_f(const Geo& G, const void* fb, int x, int y, int z,
   }
 }
 
-template <int P, bool PACK>
+template <int P, bool PACK, int Q = 15>
 __device__ inline void pull_g(const Geo& G, const void* fb, const void* gb, int x, int y, int z, int n,
-                              typename Prec<P>::T g[15]) {
+                              typename Prec<P>::T g[Q]) {
 #pragma unroll
-  for (int i = 0; i < 15; ++i) {
-    int s = (i == 0) ? n : pull_src(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2));
+  for (int i = 0; i < Q; ++i) {
+    int s = (i == 0) ? n : pull_src(G, x, y, z, cq<Q>(i, 0), cq<Q>(i, 1), cq<Q>(i, 2));
     g[i] = (s >= 0) ? Lat<P, PACK>::ldg(fb, gb, G.pitch, i, s) : Lat<P, PACK>::ldg(fb, gb, G.pitch, opp(i), n);
   }
 }
@@ -234,6 +245,39 @@ __device__ inline void flow_macro(const Coef<T>& C, const T g[15], T phi, T mu, 
   T ugr = m.u[0] * m.gr[0] + m.u[1] * m.gr[1] + m.u[2] * m.gr[2];
   // c_s^2 / (1 - w_0) = 3/7 and rho s_0(u) = -rho |u|^2 / 3 (Eq. 30)
   m.p = (T)(3.0 / 7.0) * (sum_nz + (T)0.5 * ugr - m.rho * uu / 3);
+}
+
+// The same on D3Q19 (weights 1/3, 1/18, 1/36): c_s^2 / (1 - w_0) = 1/2 and
+// rho s_0(u) = -rho |u|^2 / 2 in Eq. 30.
+template <class T>
+__device__ inline void flow_macro19(const Coef<T>& C, const T g[19], T phi, T mu, const T gphi[3], T lapmu,
+                                    Macro<T>& m) {
+  m.phi = phi;
+  m.mu = mu;
+  m.rho = (1 + phi) / 2 * C.rho_l + (1 - phi) / 2 * C.rho_g;
+  T half_dr = C.drho / 2;
+  T j[3] = {0, 0, 0}, sum_nz = 0;
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    sum_nz += g[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (c19(i, a) != 0) j[a] += c19(i, a) > 0 ? g[i] : -g[i];
+  }
+  T Fs[3], Gb[3];
+  T ml = C.mob * lapmu;
+  T denom = m.rho - (T)0.25 * C.drho * ml;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m.gr[a] = half_dr * gphi[a];
+    Fs[a] = mu * gphi[a];
+    Gb[a] = (m.rho - C.rho_ref) * C.grav[a];
+    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) / denom;
+    m.F[a] = Fs[a] + half_dr * ml * m.u[a] + Gb[a];
+  }
+  T uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  T ugr = m.u[0] * m.gr[0] + m.u[1] * m.gr[1] + m.u[2] * m.gr[2];
+  m.p = (T)0.5 * (sum_nz + (T)0.5 * ugr - m.rho * uu / 2);
 }
 
 // D3Q7 collision in moment space (Eqs. 15, 17, 18, 11): m = M f;
@@ -369,6 +413,60 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
   g[14] = P4 - Q4;
 }
 
+
+// D3Q19 collision.  With S^g = 1 except lambda on the five stress moments
+// (rows 3pxx, pww, pxy, pyz, pxz of d'Humieres' basis, squared norms 36, 12,
+// 4, 4, 4), m* = m - S(m - m^eq) + (I - S/2) m_T with m^eq = Gamma g^eq and
+// m_T = Gamma T is, after Gamma^-1,
+//   g* = g^eq + T/2 - (lambda - 1) Gamma^-1 P Gamma (g - g^eq + T/2),
+// P the projector on the stress moments: only those five moments are formed.
+// g^eq from Eqs. 21-22, T from Eq. 28 (F = F_s + F_a + G), both in velocity
+// space.
+template <class T>
+__device__ inline void collide_ns19(const Coef<T>& C, T g[19], const Macro<T>& M) {
+  const T* u = M.u;
+  const T* F = M.F;
+  const T rho = M.rho, p = M.p;
+  const T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
+  // Eq. 28: T_i = 3 [s_i (c_i - u).(a + F) + w_i (c_i - u).F], a = c_s^2 grad rho
+  T AF[3], uAF = 0, uF = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    AF[a] = M.gr[a] * (T)(1.0 / 3.0) + F[a];
+    uAF += u[a] * AF[a];
+    uF += u[a] * F[a];
+  }
+  T base[19], m9 = 0, m11 = 0, m13 = 0, m14 = 0, m15 = 0;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int cx = c19(i, 0), cy = c19(i, 1), cz = c19(i, 2);
+    const T w = i == 0 ? (T)(1.0 / 3.0) : (i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0));
+    const T cu = cx * u[0] + cy * u[1] + cz * u[2];
+    const T si = w * (3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
+    const T geq = 3 * p * (i == 0 ? w - 1 : w) + rho * si;
+    const T cAF = cx * AF[0] + cy * AF[1] + cz * AF[2];
+    const T cF = cx * F[0] + cy * F[1] + cz * F[2];
+    const T Ti = 3 * (si * (cAF - uAF) + w * (cF - uF));
+    base[i] = geq + Ti / 2;
+    const T d = g[i] - base[i] + Ti;  // g - g^eq + T/2
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    m9 += (3 * cx * cx - c2) * d;
+    m11 += (cy * cy - cz * cz) * d;
+    m13 += (cx * cy) * d;
+    m14 += (cy * cz) * d;
+    m15 += (cx * cz) * d;
+  }
+  const T k = C.lg[9] - 1;
+  const T b9 = k * m9 * (T)(1.0 / 36.0), b11 = k * m11 * (T)(1.0 / 12.0);
+  const T b13 = k * m13 / 4, b14 = k * m14 / 4, b15 = k * m15 / 4;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const int cx = c19(i, 0), cy = c19(i, 1), cz = c19(i, 2);
+    const int c2 = cx * cx + cy * cy + cz * cz;
+    g[i] = base[i] - ((3 * cx * cx - c2) * b9 + (cy * cy - cz * cz) * b11 + (cx * cy) * b13 + (cy * cz) * b14 +
+                      (cx * cz) * b15);
+  }
+}
 
 template <class T>
 __device__ inline bool all_finite(const T* v, int k) {

@@ -194,19 +194,19 @@ __device__ inline void pull_f7(const Geo& G, const void* fb, const Column& c, co
   (void)sizeof(S0);
 }
 
-// The fifteen g (PACK: only g_0 and the corners g_7..g_14).
-template <int P, bool PACK, bool XYWALL>
-__device__ inline void pull_g15(const Geo& G, const void* gb, const Column& c, const Plane& p, int zo, int xy,
-                                typename Prec<P>::T g[15]) {
+// The Q g of the NSE lattice (PACK, D3Q15 only: g_0 and the corners g_7..g_14).
+template <int P, bool PACK, bool XYWALL, int Q>
+__device__ inline void pull_gq(const Geo& G, const void* gb, const Column& c, const Plane& p, int zo, int xy,
+                               typename Prec<P>::T g[Q]) {
   using L = Lat<P, PACK>;
   using T = typename Prec<P>::T;
   using S = typename L::S;
   const S* arr = (const S*)gb;
-  S raw[15];
+  S raw[Q];
   raw[0] = ld_at(arr + zo, xy);
 #pragma unroll
-  for (int i = PACK ? 7 : 1; i < 15; ++i) {
-    const int cx = c15(i, 0), cy = c15(i, 1), cz = c15(i, 2);
+  for (int i = PACK ? 7 : 1; i < Q; ++i) {
+    const int cx = cq<Q>(i, 0), cy = cq<Q>(i, 1), cz = cq<Q>(i, 2);
     if constexpr (XYWALL) {
       const bool b = bounced<XYWALL>(c, p, cx, cy, cz);
       const int idx = b ? zo + xy : source(c, p, cx, cy, cz);
@@ -224,7 +224,7 @@ __device__ inline void pull_g15(const Geo& G, const void* gb, const Column& c, c
   __builtin_amdgcn_sched_barrier(0);
   g[0] = (T)raw[0];
 #pragma unroll
-  for (int i = PACK ? 7 : 1; i < 15; ++i) g[i] = (T)raw[i];
+  for (int i = PACK ? 7 : 1; i < Q; ++i) g[i] = (T)raw[i];
 }
 
 // Eq. 36 at a ring position c of the middle plane pc, with the planes below
@@ -383,14 +383,15 @@ struct MuMaker {
 template <int P>
 constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
 
-// The coupled step of logical block lb of one lattice (NT: streaming stores).
-template <int P, int TY, bool XYWALL, bool NT>
+// The coupled step of logical block lb of one lattice (NT: streaming stores;
+// Q: velocities of the NSE lattice, 15 or 19).
+template <int P, int TY, bool XYWALL, bool NT, int Q = 15>
 __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                                   const Tiling& TL, int lb) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 2>;
   using MU = MuMaker<P, TY>;
-  constexpr bool PACK = packed<P, true>();
+  constexpr bool PACK = packed<P, true>() && Q == 15;
   using L = Lat<P, PACK>;
   using LD = PhiLoader<P, TY, 2, XYWALL, PACK>;
   using QT = typename LD::QT;
@@ -435,7 +436,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     if (!own) continue;
     const int zo = z * G.nx * G.ny;
     const Plane p = make_plane(G, z);
-    T f[7], g[15];
+    T f[7], g[Q];
     const QT* q = sfq[(z + 9) % 3];
     if constexpr (PACK) {
       f[0] = (T)__builtin_bit_cast(float, (uint32_t)q[threadIdx.x]);
@@ -449,7 +450,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
 #pragma unroll
       for (int i = 0; i < 7; ++i) f[i] = (T)q[i * R::NT + threadIdx.x];
     }
-    pull_g15<P, PACK, XYWALL>(G, gin, col, p, zo, col_xy, g);
+    pull_gq<P, PACK, XYWALL, Q>(G, gin, col, p, zo, col_xy, g);
     T phi = phi_of(f);
     T gphi[3];
     grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi);
@@ -457,7 +458,8 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     T mu = mc[mu_c];
     T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c);
     Macro<T> M;
-    flow_macro(C, g, phi, mu, gphi, lapmu, M);
+    if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
+    else flow_macro(C, g, phi, mu, gphi, lapmu, M);
     T dphiu[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -467,7 +469,8 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
       st_at<NT>(h, col_xy, pu);
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
-    collide_ns(C, g, M);
+    if constexpr (Q == 19) collide_ns19(C, g, M);
+    else collide_ns(C, g, M);
     using S0 = typename L::S0;
     using S = typename L::S;
     st_at<NT>(L::f0(fo) + zo, col_xy, (S0)f[0]);
@@ -484,16 +487,16 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
 #pragma unroll
       for (int i = 1; i < 7; ++i) st_at<NT>(fa + ((size_t)(i - 1) * G.pitch + zo), col_xy, (S)f[i]);
 #pragma unroll
-      for (int i = 0; i < 15; ++i) st_at<NT>(ga + ((size_t)i * G.pitch + zo), col_xy, (S)g[i]);
+      for (int i = 0; i < Q; ++i) st_at<NT>(ga + ((size_t)i * G.pitch + zo), col_xy, (S)g[i]);
     }
-    if (!(all_finite(f, 7) && all_finite(g, 15))) *B.flag = 1;
+    if (!(all_finite(f, 7) && all_finite(g, Q))) *B.flag = 1;
   }
 }
 
-template <int P, int TY, bool XYWALL, bool NT>
+template <int P, int TY, bool XYWALL, bool NT, int Q>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
-  fused_body<P, TY, XYWALL, NT>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
+  fused_body<P, TY, XYWALL, NT, Q>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
 }
 
 // Many lattices in one launch (continuous batching): the blocks of all
@@ -618,7 +621,16 @@ hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
   if (mode == MPLB_COUPLED) {
     Tiling tl = make_tiling(G, kTY, 16);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-    hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+  } else if (mode == MPLB_COUPLED_Q19) {
+    // D3Q19 is built for FP64 and FP32 storage
+    if constexpr (P == MPLB_F64 || P == MPLB_F32) {
+      Tiling tl = make_tiling(G, kTY, 16);
+      dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
+      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 19>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    } else {
+      return hipErrorInvalidValue;
+    }
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
@@ -764,8 +776,9 @@ size_t fused_stream_threshold() { return kStreamBytes; }
 
 size_t fused_step_bytes(int P, int mode, long long N) {
   // populations and history read and written once per update
-  size_t per = mode == MPLB_COUPLED ? (P == MPLB_F64 ? 400 : (P == MPLB_F32 ? 200 : 116))
-                                    : (P == MPLB_F64 ? 128 : 64);
+  size_t per = mode == MPLB_COUPLED       ? (P == MPLB_F64 ? 400 : (P == MPLB_F32 ? 200 : 116))
+               : mode == MPLB_COUPLED_Q19 ? (P == MPLB_F64 ? 464 : 232)
+                                          : (P == MPLB_F64 ? 128 : 64);
   return per * (size_t)N;
 }
 

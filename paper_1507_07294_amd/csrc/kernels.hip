@@ -29,7 +29,12 @@ using namespace dev;
 // ------------------------------------------------------------------ kernels
 constexpr int kBlock = 256;
 
-template <int P, bool COUPLED>
+// Q: velocities of the NSE lattice (15 or 19); the 16-bit packing of f_i
+// with g_i exists for D3Q15 only.
+template <int P, bool COUPLED, int Q>
+constexpr bool packed_q() { return packed<P, COUPLED>() && Q == 15; }
+
+template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_phi(Geo G, Bufs B, int cur) {
   using T = typename Prec<P>::T;
   int n = blockIdx.x * kBlock + threadIdx.x;
@@ -37,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_phi(Geo G, Bufs B, int cur) {
   int x, y, z;
   decode(G, n, x, y, z);
   T f[7];
-  pull_f<P, packed<P, COUPLED>()>(G, B.f[cur], x, y, z, n, f);
+  pull_f<P, packed_q<P, COUPLED, Q>()>(G, B.f[cur], x, y, z, n, f);
   ((T*)B.phi)[n] = phi_of(f);
 }
 
@@ -57,26 +62,27 @@ __global__ void __launch_bounds__(kBlock) k_mu(Geo G, Coef<typename Prec<P>::T> 
 
 // Macroscopic state of node n at the current level (phi and mu arrays must
 // hold this level).  Returns false if a pulled population is non-finite.
-template <int P, bool COUPLED>
+template <int P, bool COUPLED, int Q = 15>
 __device__ inline bool node_macro(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur, int n,
                                   Macro<typename Prec<P>::T>& M) {
   using T = typename Prec<P>::T;
   int x, y, z;
   decode(G, n, x, y, z);
-  constexpr bool PK = packed<P, COUPLED>();
+  constexpr bool PK = packed_q<P, COUPLED, Q>();
   T f[7];
   pull_f<P, PK>(G, B.f[cur], x, y, z, n, f);
   T phi = phi_of(f);
   bool ok = all_finite(f, 7);
   if (COUPLED) {
-    T g[15];
-    pull_g<P, PK>(G, B.f[cur], B.g[cur], x, y, z, n, g);
-    ok = ok && all_finite(g, 15);
+    T g[Q];
+    pull_g<P, PK, Q>(G, B.f[cur], B.g[cur], x, y, z, n, g);
+    ok = ok && all_finite(g, Q);
     const T* mus = (const T*)B.mu;
     T mu = mus[n], gphi[3], lapphi, gd[3], lapmu;
     grad_lap(G, (const T*)B.phi, x, y, z, phi, gphi, lapphi, true);
     grad_lap(G, mus, x, y, z, mu, gd, lapmu, false);
-    flow_macro(C, g, phi, mu, gphi, lapmu, M);
+    if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
+    else flow_macro(C, g, phi, mu, gphi, lapmu, M);
   } else {
     T gr[3], lap;
     grad_lap(G, (const T*)B.phi, x, y, z, phi, gr, lap, false);
@@ -91,13 +97,13 @@ __device__ inline bool node_macro(const Geo& G, const Coef<typename Prec<P>::T>&
   return ok;
 }
 
-template <int P, bool COUPLED>
+template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_macro(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, int field) {
   using T = typename Prec<P>::T;
   int n = blockIdx.x * kBlock + threadIdx.x;
   if (n >= G.N) return;
   Macro<T> M;
-  node_macro<P, COUPLED>(G, C, B, cur, n, M);
+  node_macro<P, COUPLED, Q>(G, C, B, cur, n, M);
   T v = 0;
   switch (field) {
     case MPLB_PHI: v = M.phi; break;
@@ -119,25 +125,25 @@ __device__ inline double wave_sum(double v) {
 
 // Per-block FP64 partial sums of phi, j = sum_i c_i g_i, F and the count of
 // non-finite nodes; grid-stride over nodes, one slot of 8 doubles per block.
-template <int P, bool COUPLED>
+template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_totals(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {
   using T = typename Prec<P>::T;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int n = blockIdx.x * kBlock + threadIdx.x; n < G.N; n += gridDim.x * kBlock) {
     Macro<T> M;
-    bool ok = node_macro<P, COUPLED>(G, C, B, cur, n, M);
+    bool ok = node_macro<P, COUPLED, Q>(G, C, B, cur, n, M);
     acc[0] += (double)M.phi;
     if (COUPLED) {
       int x, y, z;
       decode(G, n, x, y, z);
-      T g[15];
-      pull_g<P, packed<P, COUPLED>()>(G, B.f[cur], B.g[cur], x, y, z, n, g);
-      double gd[15];
-      for (int i = 0; i < 15; ++i) gd[i] = (double)g[i];
-      for (int i = 0; i < 15; ++i) {
-        acc[1] += c15(i, 0) * gd[i];
-        acc[2] += c15(i, 1) * gd[i];
-        acc[3] += c15(i, 2) * gd[i];
+      T g[Q];
+      pull_g<P, packed_q<P, COUPLED, Q>(), Q>(G, B.f[cur], B.g[cur], x, y, z, n, g);
+      double gd[Q];
+      for (int i = 0; i < Q; ++i) gd[i] = (double)g[i];
+      for (int i = 0; i < Q; ++i) {
+        acc[1] += cq<Q>(i, 0) * gd[i];
+        acc[2] += cq<Q>(i, 1) * gd[i];
+        acc[3] += cq<Q>(i, 2) * gd[i];
       }
       acc[4] += (double)M.F[0];
       acc[5] += (double)M.F[1];
@@ -253,7 +259,7 @@ __global__ void __launch_bounds__(kBlock) k_cvt_in(const double* src, T* dst, in
 // Equilibrium populations at every node (Eqs. 5, 21-22 with p = 0), written
 // to the storage slot each node will pull them from, so that the first step
 // sees f = f^eq and g = g^eq at every node.
-template <int P, bool COUPLED>
+template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {
   using T = typename Prec<P>::T;
   int n = blockIdx.x * kBlock + threadIdx.x;
@@ -279,20 +285,21 @@ __global__ void __launch_bounds__(kBlock) k_init(Geo G, Coef<typename Prec<P>::T
 #pragma unroll
   for (int i = 0; i < 7; ++i) {
     int s = (i == 0) ? n : pull_src(G, x, y, z, c7(i, 0), c7(i, 1), c7(i, 2));
-    if (s >= 0) Lat<P, packed<P, COUPLED>()>::stf(B.f[cur], G.pitch, i, s, feq[i]);
-    else Lat<P, packed<P, COUPLED>()>::stf(B.f[cur], G.pitch, opp(i), n, feq[i]);
+    if (s >= 0) Lat<P, packed_q<P, COUPLED, Q>()>::stf(B.f[cur], G.pitch, i, s, feq[i]);
+    else Lat<P, packed_q<P, COUPLED, Q>()>::stf(B.f[cur], G.pitch, opp(i), n, feq[i]);
   }
   if (COUPLED) {
     T rho = (1 + phi) / 2 * C.rho_l + (1 - phi) / 2 * C.rho_g;
     T uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
-    for (int i = 0; i < 15; ++i) {
-      T w = (i == 0) ? (T)(2.0 / 9.0) : (i < 7 ? (T)(1.0 / 9.0) : (T)(1.0 / 72.0));
-      T cu = c15(i, 0) * u[0] + c15(i, 1) * u[1] + c15(i, 2) * u[2];
+    for (int i = 0; i < Q; ++i) {
+      T w = Q == 19 ? ((i == 0) ? (T)(1.0 / 3.0) : (i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0)))
+                    : ((i == 0) ? (T)(2.0 / 9.0) : (i < 7 ? (T)(1.0 / 9.0) : (T)(1.0 / 72.0)));
+      T cu = cq<Q>(i, 0) * u[0] + cq<Q>(i, 1) * u[1] + cq<Q>(i, 2) * u[2];
       T geq = rho * w * (3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);  // Eq. 21 with p = 0
-      int s = (i == 0) ? n : pull_src(G, x, y, z, c15(i, 0), c15(i, 1), c15(i, 2));
-      if (s >= 0) Lat<P, packed<P, COUPLED>()>::stg(B.f[cur], B.g[cur], G.pitch, i, s, geq);
-      else Lat<P, packed<P, COUPLED>()>::stg(B.f[cur], B.g[cur], G.pitch, opp(i), n, geq);
+      int s = (i == 0) ? n : pull_src(G, x, y, z, cq<Q>(i, 0), cq<Q>(i, 1), cq<Q>(i, 2));
+      if (s >= 0) Lat<P, packed_q<P, COUPLED, Q>()>::stg(B.f[cur], B.g[cur], G.pitch, i, s, geq);
+      else Lat<P, packed_q<P, COUPLED, Q>()>::stg(B.f[cur], B.g[cur], G.pitch, opp(i), n, geq);
     }
   }
   if (COUPLED) {
@@ -326,10 +333,10 @@ __global__ void k_fill_zero(T* p, int count) {
   if (i < count) p[i] = (T)0;
 }
 
-template <int P, bool COUPLED>
+template <int P, bool COUPLED, int Q = 15>
 __global__ void k_poke(Geo G, Bufs B, int cur, int set, int i, int n, double v) {
   using T = typename Prec<P>::T;
-  using L = Lat<P, packed<P, COUPLED>()>;
+  using L = Lat<P, packed_q<P, COUPLED, Q>()>;
   if (set == 0) L::stf(B.f[cur], G.pitch, i, n, (T)v);
   else L::stg(B.f[cur], B.g[cur], G.pitch, i, n, (T)v);
 }
@@ -354,6 +361,8 @@ hipError_t macro_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs
   using T = typename Prec<P>::T;
   Coef<T> C = cast_coef<T>(Cd);
   if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_macro<P, true>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur, field);
+  else if (mode == MPLB_COUPLED_Q19)
+    hipLaunchKernelGGL((k_macro<P, true, 19>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur, field);
   else hipLaunchKernelGGL((k_macro<P, false>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur, field);
   return hipGetLastError();
 }
@@ -365,6 +374,8 @@ hipError_t totals_impl(int mode, const Geo& G, const Coef<double>& Cd, const Buf
   int blocks = (G.N + kBlock - 1) / kBlock;
   if (blocks > kRedSlots) blocks = kRedSlots;
   if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_totals<P, true>), dim3(blocks), dim3(kBlock), 0, s, G, C, B, cur);
+  else if (mode == MPLB_COUPLED_Q19)
+    hipLaunchKernelGGL((k_totals<P, true, 19>), dim3(blocks), dim3(kBlock), 0, s, G, C, B, cur);
   else hipLaunchKernelGGL((k_totals<P, false>), dim3(blocks), dim3(kBlock), 0, s, G, C, B, cur);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -377,6 +388,8 @@ hipError_t init_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs&
   using T = typename Prec<P>::T;
   Coef<T> C = cast_coef<T>(Cd);
   if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_init<P, true>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur);
+  else if (mode == MPLB_COUPLED_Q19)
+    hipLaunchKernelGGL((k_init<P, true, 19>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur);
   else hipLaunchKernelGGL((k_init<P, false>), grid_for(G.N), dim3(kBlock), 0, s, G, C, B, cur);
   return hipGetLastError();
 }
@@ -395,6 +408,8 @@ hipError_t init_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs&
 hipError_t launch_phi(int P, int mode, const Geo& G, const Bufs& B, int cur, hipStream_t s) {
   MPLB_DISPATCH(P, {
     if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_phi<PP, true>), grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
+    else if (mode == MPLB_COUPLED_Q19)
+      hipLaunchKernelGGL((k_phi<PP, true, 19>), grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
     else hipLaunchKernelGGL((k_phi<PP, false>), grid_for(G.N), dim3(kBlock), 0, s, G, B, cur);
     return hipGetLastError();
   })
@@ -462,6 +477,8 @@ hipError_t launch_poke(int P, int mode, const Geo& G, const Bufs& B, int cur, in
                        hipStream_t s) {
   MPLB_DISPATCH(P, {
     if (mode == MPLB_COUPLED) hipLaunchKernelGGL((k_poke<PP, true>), dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
+    else if (mode == MPLB_COUPLED_Q19)
+      hipLaunchKernelGGL((k_poke<PP, true, 19>), dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
     else hipLaunchKernelGGL((k_poke<PP, false>), dim3(1), dim3(1), 0, s, G, B, cur, set, i, n, v);
     return hipGetLastError();
   })

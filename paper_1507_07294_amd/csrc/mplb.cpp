@@ -40,10 +40,11 @@ Plan make_plan(long long N, int prec, int mode) {
   // 16-bit populations of the coupled model: f_i and g_i (i = 1..6) share
   // 32-bit words in the f buffer; the g buffer keeps g_0 and the 8 corners
   bool pack = mode == MPLB_COUPLED && sS == 2;
+  const int q = mode == MPLB_COUPLED_Q19 ? 19 : 15;  // NSE lattice
   p.f = align_up(p.pitch * s0 + 6 * p.pitch * (pack ? 4 : sS), A);
-  p.g = mode == MPLB_COUPLED ? align_up((pack ? 9 : 15) * p.pitch * sS, A) : 0;
+  p.g = mode != MPLB_CHE_ONLY ? align_up((pack ? 9 : q) * p.pitch * sS, A) : 0;
   // (phi u) history: 3 words (coupled); phi alone where u is prescribed
-  p.phiu = align_up((mode == MPLB_COUPLED ? 3 : 1) * p.pitch * sT, A);
+  p.phiu = align_up((mode != MPLB_CHE_ONLY ? 3 : 1) * p.pitch * sT, A);
   p.phi = align_up(p.pitch * sT, A);
   p.mu = align_up(p.pitch * sT, A);
   p.ufield = mode == MPLB_CHE_ONLY ? align_up(3 * p.pitch * sT, A) : 0;
@@ -56,6 +57,13 @@ Plan make_plan(long long N, int prec, int mode) {
 
 // Node indices are 32-bit, and the step kernel forms in-plane byte offsets
 // in 32 bits (nx*ny elements of up to 8 bytes).
+// modes and the precisions each supports
+bool valid_mode(int mode, int precision) {
+  if (precision < MPLB_F64 || precision > MPLB_F32_BF16) return false;
+  if (mode == MPLB_COUPLED || mode == MPLB_CHE_ONLY) return true;
+  return mode == MPLB_COUPLED_Q19 && (precision == MPLB_F64 || precision == MPLB_F32);
+}
+
 bool valid_dims(int nx, int ny, int nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   long long N = (long long)nx * ny * nz;
@@ -126,9 +134,7 @@ const char* mplb_strerror(int code) {
 const char* mplb_last_error(const mplb_t* h) { return h ? h->err.c_str() : "null handle"; }
 
 int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes) {
-  if (!bytes || !valid_dims(nx, ny, nz) || precision < MPLB_F64 || precision > MPLB_F32_BF16 ||
-      (mode != MPLB_COUPLED && mode != MPLB_CHE_ONLY))
-    return MPLB_E_INVAL;
+  if (!bytes || !valid_dims(nx, ny, nz) || !valid_mode(mode, precision)) return MPLB_E_INVAL;
   *bytes = make_plan((long long)nx * ny * nz, precision, mode).total;
   return MPLB_OK;
 }
@@ -137,9 +143,7 @@ int mplb_create(int nx, int ny, int nz, const int bc[3], int precision, int mode
                 size_t arena_bytes, mplb_t** out) {
   if (!out) return MPLB_E_INVAL;
   *out = nullptr;
-  if (!bc || !valid_dims(nx, ny, nz) || precision < MPLB_F64 || precision > MPLB_F32_BF16 ||
-      (mode != MPLB_COUPLED && mode != MPLB_CHE_ONLY))
-    return MPLB_E_INVAL;
+  if (!bc || !valid_dims(nx, ny, nz) || !valid_mode(mode, precision)) return MPLB_E_INVAL;
   for (int a = 0; a < 3; ++a)
     if (bc[a] != MPLB_PERIODIC && bc[a] != MPLB_WALL) return MPLB_E_INVAL;
   mplb_t* h = new (std::nothrow) mplb_t();
@@ -289,7 +293,7 @@ int mplb_init(mplb_t* h, const double* phi0, const double* u0) {
   size_t sT = comp_size(h->prec);
   int rc = upload_field(h, phi0, h->B.phi);
   if (rc) return rc;
-  if (h->mode == MPLB_COUPLED) {
+  if (h->mode != MPLB_CHE_ONLY) {
     for (int a = 0; a < 3; ++a) {
       void* dst = (char*)h->B.phiu + (size_t)a * h->G.pitch * sT;
       if (u0) {
@@ -457,7 +461,7 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   }
   mplb_t* h0 = hs[0];
   hipStream_t s = h0->stream;
-  if (h0->mode != MPLB_COUPLED) {  // CHE-only lattices step one after another on the stream
+  if (h0->mode != MPLB_COUPLED) {  // CHE-only and D3Q19 lattices step one after another on the stream
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < count; ++i) {
         int rc = enqueue_step(hs[i], s);
@@ -534,7 +538,7 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
 
 static int prepare_macro(mplb_t* h) {
   HIPCHK(h, launch_phi(h->prec, h->mode, h->G, h->B, h->cur, h->stream));
-  if (h->mode == MPLB_COUPLED) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
+  if (h->mode != MPLB_CHE_ONLY) HIPCHK(h, launch_mu(h->prec, h->G, h->C, h->B, h->stream));
   set_vel_time(h);
   return MPLB_OK;
 }
@@ -629,7 +633,8 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int streaming, voi
 
 int mplb_poke(mplb_t* h, int set, int i, long node, double value) {
   if (!h || set < 0 || set > 1 || i < 0 || node < 0 || node >= h->G.N) return MPLB_E_INVAL;
-  if ((set == 0 && i > 6) || (set == 1 && (i > 14 || h->mode != MPLB_COUPLED))) return MPLB_E_INVAL;
+  const int q = h->mode == MPLB_COUPLED_Q19 ? 19 : 15;
+  if ((set == 0 && i > 6) || (set == 1 && (i >= q || h->mode == MPLB_CHE_ONLY))) return MPLB_E_INVAL;
   if (!h->have_init) return fail(h, MPLB_E_STATE, "poke before init");
   HIPCHK(h, launch_poke(h->prec, h->mode, h->G, h->B, h->cur, set, i, (int)node, value, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));

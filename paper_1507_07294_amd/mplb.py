@@ -24,7 +24,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "mplb.h")
 MPLB_OK, MPLB_E_INVAL, MPLB_E_NOMEM, MPLB_E_DEVICE, MPLB_E_STATE, MPLB_E_NONFINITE = 0, 1, 2, 3, 4, 5
 MPLB_PERIODIC, MPLB_WALL = 0, 1
 MPLB_F64, MPLB_F32, MPLB_F32_F16, MPLB_F32_BF16 = 0, 1, 2, 3
-MPLB_COUPLED, MPLB_CHE_ONLY = 0, 1
+MPLB_COUPLED, MPLB_CHE_ONLY, MPLB_COUPLED_Q19 = 0, 1, 2
 MPLB_PHI, MPLB_RHO, MPLB_MU, MPLB_UX, MPLB_UY, MPLB_UZ, MPLB_P = range(7)
 MPLB_VEL_ZERO, MPLB_VEL_FIELD, MPLB_VEL_ZALESAK, MPLB_VEL_DEFORM = 0, 1, 2, 3
 
@@ -303,7 +303,7 @@ def mplb_copy_probe(src, dst, nbytes, streaming=False, stream=None):
 
 def from_workload(w, precision="f64", arena=None):
     """A lattice set up and initialised from a workloads.Workload."""
-    mode = MPLB_COUPLED if w.coupled else MPLB_CHE_ONLY
+    mode = (MPLB_COUPLED_Q19 if getattr(w, "nse_q", 15) == 19 else MPLB_COUPLED) if w.coupled else MPLB_CHE_ONLY
     lt = Lattice(w.shape, w.bc, precision, mode, w.params, arena=arena)
     if not w.coupled:
         v = w.velocity or {"kind": "zero"}

@@ -69,6 +69,56 @@ def test_coupled_f32(shape, bc, seed):
     _compare(w, [1, 10, 100], "f32", F32_TOL)
 
 
+@pytest.mark.parametrize("shape,bc,seed", [
+    ((24, 20, 18), (0, 0, 1), 41),  # walls in z, odd box
+    ((70, 37, 29), (0, 0, 0), 42),  # several tiles and a ragged tail, periodic
+    ((9, 10, 11), (1, 1, 1), 43),   # walls on every axis
+])
+def test_coupled_q19_f64(shape, bc, seed):
+    """The D3Q19 variant of the NSE lattice against the oracle's dense
+    moment-space collision, FP64 (the kernel collides by projection onto the
+    stress moments)."""
+    w = wl.perturbed_case(shape, bc, seed, coupled=True, ratio=(2.5, 4.0, 7.0)[seed % 3])
+    w.nse_q = 19
+    _compare(w, [1, 10, 60], "f64", F64_TOL)
+
+
+def test_coupled_q19_f32():
+    w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 44, coupled=True)
+    w.nse_q = 19
+    _compare(w, [1, 10, 100], "f32", F32_TOL)
+
+
+def test_q19_totals_checkpoint_and_batch():
+    """D3Q19: FP64 totals equal the oracle's, the GPU momentum balance holds,
+    a checkpoint restores bitwise, and step_many (one lattice after another
+    for this mode) equals separate steps."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((17, 19, 23), (0, 0, 0), 45, coupled=True, gravity=(1e-5, 0, -2e-5))
+    w.nse_q = 19
+    o = helpers.oracle_for(w)
+    g = helpers.gpu_for(w, "f64")
+    for _ in range(3):
+        to, tg = o.totals(), g.totals()
+        assert np.allclose(tg, to, rtol=1e-12, atol=1e-15), (tg, to)
+        g.step(1)
+        o.step(1)
+        assert np.allclose(g.totals()[1:4], tg[1:4] + tg[4:7], rtol=0, atol=1e-13)
+    blob = g.checkpoint()
+    g.step(5)
+    after = {k: g.read(k) for k in ("phi", "ux", "p")}
+    g.restore(blob)
+    g.step(5)
+    for k, v in after.items():
+        assert np.array_equal(g.read(k), v), k
+    a, b = helpers.gpu_for(w, "f32"), helpers.gpu_for(w, "f32")
+    c = helpers.gpu_for(w, "f32")
+    mplb.mplb_step_many([a, b], 7)
+    c.step(7)
+    for k in ("phi", "uy", "p"):
+        assert np.array_equal(a.read(k), c.read(k)) and np.array_equal(b.read(k), c.read(k)), k
+
+
 @pytest.mark.parametrize("kind", ["field", "zalesak", "deformation"])
 @pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
 def test_che_only(kind, precision, tol):
