@@ -306,8 +306,23 @@ int orc_set_params(orc_t* s, const orc_params* p) {
   }
   for (int i = 0; i < 7; ++i)
     if (!(p->s_f[i] > 0 && p->s_f[i] < 2)) { snprintf(s->err, sizeof s->err, "s_f out of (0,2)"); return ORC_E_INVAL; }
+  if ((p->stencil != ORC_STENCIL_Q15 && p->stencil != ORC_STENCIL_Q7) ||
+      (p->forcing != ORC_FORCING_EQ32 && p->forcing != ORC_FORCING_EQ28)) {
+    snprintf(s->err, sizeof s->err, "unknown stencil or forcing switch");
+    return ORC_E_INVAL;
+  }
+  if (p->lambda_override)
+    for (int i = 10; i <= 13; ++i)
+      if (p->lambda_g[i] != p->lambda_g[9]) {
+        snprintf(s->err, sizeof s->err, "lambda_9..13 must be equal");
+        return ORC_E_INVAL;
+      }
   double d[6];
   orc_derived(p, d);
+  if (p->lambda_override) { /* the viscous rate given, tau_g = 1/lambda_9 (Eq. 33) */
+    d[5] = p->lambda_g[9];
+    d[4] = 1.0 / d[5];
+  }
   s->p = *p;
   s->beta = d[0]; s->kappa = d[1]; s->tau_f = d[2]; s->eta = d[3]; s->tau_g = d[4];
   s->drho = p->rho_l - p->rho_g;
@@ -485,18 +500,37 @@ void orc_mT(const double u[3], const double gr[3], const double F[3], double m[1
   m[14] = 0.0;
 }
 
-/* Eq. 35 at one node (D3Q15 weights) */
+/* Eq. 35 at one node: D3Q15 weights (default) or, with ORC_STENCIL_Q7, the
+ * D3Q7 weights w_i = A/2, c_s^2 = A (Eqs. 7-8), whose ratio is 1/2 */
 static void grad_at(const orc_t* s, const double* chi, int x, int y, int z, double out[3]) {
   out[0] = out[1] = out[2] = 0.0;
+  if (s->p.stencil == ORC_STENCIL_Q7) {
+    double w[7], cs2 = s->p.A * C_LAT * C_LAT;
+    weights7(s->p.A, w);
+    for (int i = 1; i < 7; ++i) {
+      double v = chi[stencil_nb(s, x, y, z, C7[i][0], C7[i][1], C7[i][2])];
+      for (int a = 0; a < 3; ++a) out[a] += w[i] * C_LAT * C7[i][a] * v / cs2;
+    }
+    return;
+  }
   for (int i = 1; i < 15; ++i) {
     double v = chi[stencil_nb(s, x, y, z, C15[i][0], C15[i][1], C15[i][2])];
     for (int a = 0; a < 3; ++a) out[a] += W15[i] * C_LAT * C15[i][a] * v / CS2_G;
   }
 }
 
-/* Eq. 36 at one node (D3Q15 weights) */
+/* Eq. 36 at one node, on the lattice of grad_at */
 static double lap_at(const orc_t* s, const double* chi, int x, int y, int z) {
   double c0 = chi[idx(s, x, y, z)], acc = 0.0;
+  if (s->p.stencil == ORC_STENCIL_Q7) {
+    double w[7], cs2 = s->p.A * C_LAT * C_LAT;
+    weights7(s->p.A, w);
+    for (int i = 1; i < 7; ++i) {
+      double v = chi[stencil_nb(s, x, y, z, C7[i][0], C7[i][1], C7[i][2])];
+      acc += 2.0 * w[i] * (v - c0) / cs2;
+    }
+    return acc;
+  }
   for (int i = 1; i < 15; ++i) {
     double v = chi[stencil_nb(s, x, y, z, C15[i][0], C15[i][1], C15[i][2])];
     acc += 2.0 * W15[i] * (v - c0) / CS2_G;
@@ -710,7 +744,16 @@ static void step_once(orc_t* s) {
       for (int i = 0; i < 15; ++i) mg[r] += G15[r][i] * gl[i];
     }
     orc_meq_g(s->pr[n], s->rho[n], u, mgeq);
-    orc_mT(u, gr, F, mT);
+    if (s->p.forcing == ORC_FORCING_EQ28) { /* Gamma T of Eq. 28, untruncated */
+      double T[15];
+      T_of(s, u, gr, F, T);
+      for (int r = 0; r < 15; ++r) {
+        mT[r] = 0.0;
+        for (int i = 0; i < 15; ++i) mT[r] += G15[r][i] * T[i];
+      }
+    } else {
+      orc_mT(u, gr, F, mT);
+    }
     for (int r = 0; r < 15; ++r)
       mgs[r] = mg[r] - s->lg[r] * (mg[r] - mgeq[r]) + (1.0 - s->lg[r] / 2.0) * mT[r];
     for (int i = 0; i < 15; ++i) {

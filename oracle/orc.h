@@ -48,7 +48,16 @@ typedef struct orc_params {
   double lambda_g[15]; /* S^g diagonal (Eq. 26); entries 9..13 are replaced from nu */
   double gravity[3];   /* body acceleration; G = (rho - rho_ref) * gravity */
   double rho_ref;      /* reference density of the body force (0: G = rho g) */
+  /* study switches (0 = the readings of the paper used by default) */
+  int stencil;         /* ORC_STENCIL_Q15: Eqs. 35-36 with D3Q15 weights; ORC_STENCIL_Q7: with the
+                          D3Q7 weights (central differences, 7-point Laplacian) */
+  int forcing;         /* ORC_FORCING_EQ32: the printed moments of Eq. 32; ORC_FORCING_EQ28: Gamma T of
+                          Eq. 28 exactly (D3Q15; the D3Q19 variant always uses Gamma T) */
+  int lambda_override; /* nonzero: lambda_9..13 come from lambda_g (all equal), not from nu */
 } orc_params;
+
+enum { ORC_STENCIL_Q15 = 0, ORC_STENCIL_Q7 = 1 };
+enum { ORC_FORCING_EQ32 = 0, ORC_FORCING_EQ28 = 1 };
 
 typedef struct orc_s orc_t;
 

@@ -18,6 +18,8 @@ LIB_PATH = os.environ.get("ORC_LIB_PATH") or os.path.join(_HERE, "liborc.so")
 
 PERIODIC, WALL = 0, 1
 COUPLED, CHE_ONLY, COUPLED_Q19 = 0, 1, 2
+STENCIL_Q15, STENCIL_Q7 = 0, 1
+FORCING_EQ32, FORCING_EQ28 = 0, 1
 FIELDS = {"phi": 0, "rho": 1, "mu": 2, "ux": 3, "uy": 4, "uz": 5, "p": 6}
 VEL_ZERO, VEL_FIELD, VEL_ZALESAK, VEL_DEFORM = 0, 1, 2, 3
 E_NONFINITE = 5
@@ -37,7 +39,8 @@ class OrcParams(C.Structure):
     _fields_ = [("sigma", C.c_double), ("width", C.c_double), ("rho_l", C.c_double),
                 ("rho_g", C.c_double), ("mobility", C.c_double), ("A", C.c_double),
                 ("s_f", C.c_double * 7), ("nu", C.c_double), ("lambda_g", C.c_double * 15),
-                ("gravity", C.c_double * 3), ("rho_ref", C.c_double)]
+                ("gravity", C.c_double * 3), ("rho_ref", C.c_double),
+                ("stencil", C.c_int), ("forcing", C.c_int), ("lambda_override", C.c_int)]
 
 
 _lib = None
@@ -102,6 +105,9 @@ def to_params(p) -> OrcParams:
         o.lambda_g[i] = p.lambda_g[i]
     for a in range(3):
         o.gravity[a] = p.gravity[a]
+    o.stencil = int(getattr(p, "stencil", 0))
+    o.forcing = int(getattr(p, "forcing", 0))
+    o.lambda_override = int(getattr(p, "lambda_override", 0))
     return o
 
 

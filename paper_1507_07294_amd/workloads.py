@@ -30,6 +30,10 @@ class ModelParams:
     s_f: S^f diagonal (Eq. 10).  nu: kinematic viscosity (Eq. 33), which sets
     lambda_9..lambda_13; lambda_g holds the other S^g rates (Eq. 26).
     gravity, rho_ref: body force G = (rho - rho_ref) * gravity.
+    stencil: lattice of the finite differences of Eqs. 35-36 (0: D3Q15, the
+    default reading; 1: D3Q7).  forcing: 0 uses the printed Eq. 32, 1 the
+    untruncated Gamma T of Eq. 28.  lambda_override: nonzero takes
+    lambda_9..13 from lambda_g instead of from nu.
     """
     sigma: float = 0.01
     width: float = 4.0
@@ -42,6 +46,9 @@ class ModelParams:
     lambda_g: Tuple[float, ...] = (1.0,) * 15
     gravity: Tuple[float, float, float] = (0.0, 0.0, 0.0)
     rho_ref: float = 0.0
+    stencil: int = 0
+    forcing: int = 0
+    lambda_override: int = 0
 
     def replace(self, **kw) -> "ModelParams":
         return dataclasses.replace(self, **kw)

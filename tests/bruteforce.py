@@ -106,6 +106,10 @@ class Brute:
         tau_f = 1 / params.s_f[1]
         self.eta = params.mobility / (A * (tau_f - 0.5))
         tau_g = 3 * params.nu + 0.5
+        self.stencil7 = getattr(params, "stencil", 0) == 1
+        self.forcing28 = getattr(params, "forcing", 0) == 1
+        if getattr(params, "lambda_override", 0):
+            tau_g = 1 / params.lambda_g[9]
         if q == 19:  # stress moments at 1/tau_g, the rest at 1
             lam = np.ones(19)
             lam[[9, 11, 13, 14, 15]] = 1 / tau_g
@@ -134,20 +138,28 @@ class Brute:
         nz, ny, nx = self.nz, self.ny, self.nx
         return padded[1 + c[2]:1 + c[2] + nz, 1 + c[1]:1 + c[1] + ny, 1 + c[0]:1 + c[0] + nx]
 
+    def _stencil(self):
+        """velocities, weights, c_s^2 of the finite differences (Eqs. 35-36)"""
+        if self.stencil7:
+            return self.c7, self.w7, self.cs2f
+        return self.c15, self.w15, self.cs2
+
     def grad(self, chi):
+        c, w, cs2 = self._stencil()
         P = self._pad(chi)
         out = np.zeros((3,) + chi.shape)
-        for i in range(1, 15):
-            v = self._nb(P, self.c15[i])
+        for i in range(1, len(c)):
+            v = self._nb(P, c[i])
             for a in range(3):
-                out[a] += self.w15[i] * self.c15[i][a] * v / self.cs2
+                out[a] += w[i] * c[i][a] * v / cs2
         return out
 
     def lap(self, chi):
+        c, w, cs2 = self._stencil()
         P = self._pad(chi)
         out = np.zeros(chi.shape)
-        for i in range(1, 15):
-            out += 2 * self.w15[i] * (self._nb(P, self.c15[i]) - chi) / self.cs2
+        for i in range(1, len(c)):
+            out += 2 * w[i] * (self._nb(P, c[i]) - chi) / cs2
         return out
 
     # ---- one step ----
@@ -252,7 +264,7 @@ class Brute:
         if not self.coupled:
             return f_new, g, phiu
         ge = self.geq(m["p"], m["rho"], m["u"])
-        if self.q == 19:  # no printed moment form: Gamma T of Eq. 28
+        if self.q == 19 or self.forcing28:  # Gamma T of Eq. 28, untruncated
             mt = np.einsum("ij,j...->i...", self.Gm, self.T(m["u"], m["grho"], m["F"]))
         else:
             mt = self.mT(m["u"], m["grho"], m["F"])
