@@ -89,10 +89,24 @@ typedef struct mplb_params {
   double A;            /* D3Q7 free parameter, 0 < A < 1/3 (Eq. 8); the paper fixes 0.25 */
   double s_f[7];       /* S^f (Eq. 10), each in (0,2), s_1 = s_2 = s_3 */
   double nu;           /* kinematic viscosity > 0 (Eq. 33): lambda_9..13 = 1/(3 nu + 1/2) */
-  double lambda_g[15]; /* S^g (Eq. 26), each in (0,2); entries 9..13 are replaced from nu */
+  double lambda_g[15]; /* S^g (Eq. 26), each in (0,2); entries 9..13 are replaced from nu
+                          unless lambda_override */
   double gravity[3];   /* body acceleration; G = (rho - rho_ref) gravity */
   double rho_ref;      /* reference density of the body force (0: G = rho gravity) */
+  /* study switches; 0 selects the readings used by default */
+  int stencil;         /* MPLB_STENCIL_Q15: Eqs. 35-36 with the D3Q15 weights; MPLB_STENCIL_Q7: with the
+                          D3Q7 weights (central differences and the 7-point Laplacian) */
+  int forcing;         /* MPLB_FORCING_EQ32: the printed moments of Eq. 32; MPLB_FORCING_EQ28: Gamma T of
+                          Eq. 28 untruncated, FP64 and FP32 storage only (MPLB_E_INVAL otherwise); such
+                          lattices step one after another in mplb_step_many.  The D3Q19 variant always
+                          uses Gamma T. */
+  int lambda_override; /* nonzero: lambda_9..13 are taken from lambda_g (all equal) instead of from nu */
 } mplb_params;
+
+#define MPLB_STENCIL_Q15 0
+#define MPLB_STENCIL_Q7 1
+#define MPLB_FORCING_EQ32 0
+#define MPLB_FORCING_EQ28 1
 
 typedef struct mplb_s mplb_t;
 

@@ -32,6 +32,8 @@ struct Coef {
   T velU;
   T vel_ct;               // cos(pi t / T) of the current step (deformation flow)
   T vel_ct_prev;          // the same at the previous level (step 0: the current one)
+  int stencil7;           // Eqs. 35-36 on the D3Q7 weights instead of D3Q15
+  int forcing28;          // Gamma T of Eq. 28 instead of the printed Eq. 32 (D3Q15)
 };
 
 // Compute type T, storage of f_0 (S0) and of f_1..f_6 and g (S).

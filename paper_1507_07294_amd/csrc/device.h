@@ -148,10 +148,22 @@ __device__ inline T phi_of(const T f[7]) {
 }
 
 // Eq. 35 (gradient) and Eq. 36 (Laplacian) with D3Q15 weights, c_s^2 = 1/3:
-// face neighbours weigh 1/3 (gradient) and 2/3 (Laplacian), corners 1/24 and 1/12.
+// face neighbours weigh 1/3 (gradient) and 2/3 (Laplacian), corners 1/24 and
+// 1/12.  s7: the D3Q7 weights instead (w_i / c_s^2 = 1/2: central
+// differences and the 7-point Laplacian).
 template <class T>
 __device__ inline void grad_lap(const Geo& G, const T* chi, int x, int y, int z, T c0, T gr[3], T& lap,
-                                bool want_grad) {
+                                bool want_grad, bool s7 = false) {
+  if (s7) {
+    T v[7];
+#pragma unroll
+    for (int i = 1; i < 7; ++i) v[i] = chi[stencil_nb(G, x, y, z, c7(i, 0), c7(i, 1), c7(i, 2))];
+    lap = (((v[1] - c0) + (v[2] - c0)) + ((v[3] - c0) + (v[4] - c0))) + ((v[5] - c0) + (v[6] - c0));
+    gr[0] = (T)0.5 * (v[1] - v[2]);
+    gr[1] = (T)0.5 * (v[3] - v[4]);
+    gr[2] = (T)0.5 * (v[5] - v[6]);
+    return;
+  }
   T gx = 0, gy = 0, gz = 0, lf = 0, lc = 0;
 #pragma unroll
   for (int i = 1; i < 15; ++i) {
@@ -308,19 +320,16 @@ __device__ inline void collide_che(const Coef<T>& C, T f[7], T phi, T mu, const 
   f[6] = c - b3 - b5 - b6;
 }
 
-// D3Q15 collision in moment space (Eqs. 20, 27, 31, 32): m = Gamma g;
-// m* = m - S^g (m - m^eq) + (I - S^g/2) mT; g* = Gamma^-1 m*.  Gamma's rows are
-// d'Humieres' basis on the Eq. 23 velocity order.
+// m = Gamma v for the D3Q15 basis of d'Humieres on the Eq. 23 order
+// (corner pairs (7,8) (9,10) (11,12) (13,14) are antipodal).
 template <class T>
-__device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) {
-  // face and corner combinations (corner pairs (7,8) (9,10) (11,12) (13,14) are antipodal)
+__device__ inline void gamma15(const T g[15], T m[15]) {
   T sx = g[1] + g[2], sy = g[3] + g[4], sz = g[5] + g[6];
   T dx = g[1] - g[2], dy = g[3] - g[4], dz = g[5] - g[6];
   T p1 = g[7] + g[8], p2 = g[9] + g[10], p3 = g[11] + g[12], p4 = g[13] + g[14];
   T d1 = g[7] - g[8], d2 = g[9] - g[10], d3 = g[11] - g[12], d4 = g[13] - g[14];
   T Sf = (sx + sy) + sz, Sc = (p1 + p2) + (p3 + p4);
   T Xc = (d1 + d2) + (d3 + d4), Yc = (d1 + d2) - (d3 + d4), Zc = (d1 - d2) + (d3 - d4);
-  T m[15];
   m[0] = g[0] + Sf + Sc;
   m[1] = -2 * g[0] - Sf + Sc;
   m[2] = 16 * g[0] - 4 * Sf + Sc;
@@ -336,6 +345,17 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
   m[12] = (p1 - p2) - (p3 - p4);
   m[13] = (p1 - p2) + (p3 - p4);
   m[14] = (d1 - d2) - (d3 - d4);
+}
+
+// D3Q15 collision in moment space (Eqs. 20, 27, 31, 32): m = Gamma g;
+// m* = m - S^g (m - m^eq) + (I - S^g/2) mT; g* = Gamma^-1 m*.  Gamma's rows are
+// d'Humieres' basis on the Eq. 23 velocity order.  F28: mT = Gamma T with T
+// of Eq. 28 untruncated, instead of the printed Eq. 32 (a compile-time
+// switch: the extra registers would cost the default step occupancy).
+template <bool F28 = false, class T>
+__device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) {
+  T m[15];
+  gamma15(g, m);
 
   const T* u = M.u;
   T rho = M.rho, p = M.p;
@@ -378,6 +398,22 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
   src[12] = u[1] * a[2] + u[2] * a[1];
   src[13] = u[0] * a[2] + u[2] * a[0];
   src[14] = 0;
+  if constexpr (F28) {
+    // T_i = 3 [s_i (c_i - u).(a) + w_i (c_i - u).F] with a here the sum
+    // c_s^2 grad rho + F of Eq. 28 (s_i + w_i multiplies F)
+    T Tv[15];
+    T ua = u[0] * a[0] + u[1] * a[1] + u[2] * a[2];
+#pragma unroll
+    for (int i = 0; i < 15; ++i) {
+      const T w = i == 0 ? (T)(2.0 / 9.0) : (i < 7 ? (T)(1.0 / 9.0) : (T)(1.0 / 72.0));
+      const T cu = c15(i, 0) * u[0] + c15(i, 1) * u[1] + c15(i, 2) * u[2];
+      const T si = w * (3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
+      const T ca = c15(i, 0) * a[0] + c15(i, 1) * a[1] + c15(i, 2) * a[2];
+      const T cF = c15(i, 0) * F[0] + c15(i, 1) * F[1] + c15(i, 2) * F[2];
+      Tv[i] = 3 * (si * (ca - ua) + w * (cF - uF));
+    }
+    gamma15(Tv, src);
+  }
   T ms[15];
 #pragma unroll
   for (int r = 0; r < 15; ++r) ms[r] = m[r] - C.lg[r] * (m[r] - eq[r]) + (1 - C.lg[r] / 2) * src[r];

@@ -252,19 +252,29 @@ __device__ inline void pull_gq(const Geo& G, const void* gb, const Column& c, co
 }
 
 // Eq. 36 at a ring position c of the middle plane pc, with the planes below
-// (pm) and above (pp); 2/3 per face and 1/12 per corner.
+// (pm) and above (pp); 2/3 per face and 1/12 per corner (s7: the D3Q7
+// weights, 1 per face).
 template <class T, int PX>
-__device__ inline T lap_lds(const T* pm, const T* pc, const T* pp, int c) {
+__device__ inline T lap_lds(const T* pm, const T* pc, const T* pp, int c, bool s7 = false) {
   T c0 = pc[c];
+  if (s7)
+    return (((pc[c + 1] - c0) + (pc[c - 1] - c0)) + ((pc[c + PX] - c0) + (pc[c - PX] - c0))) +
+           ((pp[c] - c0) + (pm[c] - c0));
   T lf = ((pc[c - 1] - c0) + (pc[c + 1] - c0)) + ((pc[c - PX] - c0) + (pc[c + PX] - c0)) + ((pm[c] - c0) + (pp[c] - c0));
   T lc = ((pm[c - PX - 1] - c0) + (pm[c - PX + 1] - c0)) + ((pm[c + PX - 1] - c0) + (pm[c + PX + 1] - c0)) +
          ((pp[c - PX - 1] - c0) + (pp[c - PX + 1] - c0)) + ((pp[c + PX - 1] - c0) + (pp[c + PX + 1] - c0));
   return (T)(2.0 / 3.0) * lf + (T)(1.0 / 12.0) * lc;
 }
 
-// Eq. 35: face neighbours weigh 1/3, corners 1/24.
+// Eq. 35: face neighbours weigh 1/3, corners 1/24 (s7: central differences).
 template <class T, int PX>
-__device__ inline void grad_lds(const T* pm, const T* pc, const T* pp, int c, T gr[3]) {
+__device__ inline void grad_lds(const T* pm, const T* pc, const T* pp, int c, T gr[3], bool s7 = false) {
+  if (s7) {
+    gr[0] = (T)0.5 * (pc[c + 1] - pc[c - 1]);
+    gr[1] = (T)0.5 * (pc[c + PX] - pc[c - PX]);
+    gr[2] = (T)0.5 * (pp[c] - pm[c]);
+    return;
+  }
   T a = pm[c + PX + 1], b = pm[c + PX - 1], d = pm[c - PX + 1], e = pm[c - PX - 1];
   T A = pp[c + PX + 1], Bv = pp[c + PX - 1], D = pp[c - PX + 1], E = pp[c - PX - 1];
   T cx = ((a - b) + (d - e)) + ((A - Bv) + (D - E));
@@ -396,7 +406,7 @@ struct MuMaker {
     for (int k = 0; k < MPT; ++k) {
       if (on[k]) {
         T c0 = pc[src[k]];
-        T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k]);
+        T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k], C.stencil7 != 0);
         smu[dst[k]] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
       }
     }
@@ -409,7 +419,7 @@ constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
 
 // The coupled step of logical block lb of one lattice (NT: streaming stores;
 // Q: velocities of the NSE lattice, 15 or 19).
-template <int P, int TY, bool XYWALL, bool NT, int Q = 15>
+template <int P, int TY, bool XYWALL, bool NT, int Q = 15, bool F28 = false>
 __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                                   const Tiling& TL, int lb) {
   using T = typename Prec<P>::T;
@@ -491,10 +501,11 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     T phi = phi_of(f);
     T gphi[3];
-    grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi);
+    grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi,
+                       C.stencil7 != 0);
     const T* mc = smu[(z + 6) % 3];
     T mu = mc[mu_c];
-    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c);
+    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c, C.stencil7 != 0);
     Macro<T> M;
     if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
     else flow_macro(C, g, phi, mu, gphi, lapmu, M);
@@ -508,7 +519,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
     if constexpr (Q == 19) collide_ns19(C, g, M);
-    else collide_ns(C, g, M);
+    else collide_ns<F28>(C, g, M);
     using S0 = typename L::S0;
     using S = typename L::S;
     st_at<NT>(L::f0(fo) + zo, col_xy, (S0)f[0]);
@@ -531,10 +542,10 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   }
 }
 
-template <int P, int TY, bool XYWALL, bool NT, int Q>
+template <int P, int TY, bool XYWALL, bool NT, int Q, bool F28 = false>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
-  fused_body<P, TY, XYWALL, NT, Q>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
+  fused_body<P, TY, XYWALL, NT, Q, F28>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
 }
 
 // Many lattices in one launch (continuous batching): the blocks of all
@@ -593,7 +604,8 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
 #pragma unroll
     for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * R::NT + threadIdx.x];
     T phi = phi_of(f);
-    T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c);
+    T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c,
+                              C.stencil7 != 0);
     T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
     T u[3], up[3];
     presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
@@ -624,6 +636,7 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
   for (int i = 0; i < 7; ++i) o.sf[i] = (T)c.sf[i];
   for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
   o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
+  o.stencil7 = c.stencil7; o.forcing28 = c.forcing28;
   return o;
 }
 
@@ -659,7 +672,14 @@ hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
   if (mode == MPLB_COUPLED) {
     Tiling tl = make_tiling(G, kTY, 16);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-    hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    if (C.forcing28) {  // the untruncated forcing is built for FP64 and FP32 storage
+      if constexpr (P == MPLB_F64 || P == MPLB_F32)
+        hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15, true>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+      else
+        return hipErrorInvalidValue;
+    } else {
+      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    }
   } else if (mode == MPLB_COUPLED_Q19) {
     // D3Q19 is built for FP64 and FP32 storage
     if constexpr (P == MPLB_F64 || P == MPLB_F32) {

@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(kBlock) k_mu(Geo G, Coef<typename Prec<P>::T> 
   decode(G, n, x, y, z);
   const T* phi = (const T*)B.phi;
   T c0 = phi[n], gr[3], lap;
-  grad_lap(G, phi, x, y, z, c0, gr, lap, false);
+  grad_lap(G, phi, x, y, z, c0, gr, lap, false, C.stencil7 != 0);
   ((T*)B.mu)[n] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
 }
 
@@ -79,13 +79,13 @@ __device__ inline bool node_macro(const Geo& G, const Coef<typename Prec<P>::T>&
     ok = ok && all_finite(g, Q);
     const T* mus = (const T*)B.mu;
     T mu = mus[n], gphi[3], lapphi, gd[3], lapmu;
-    grad_lap(G, (const T*)B.phi, x, y, z, phi, gphi, lapphi, true);
-    grad_lap(G, mus, x, y, z, mu, gd, lapmu, false);
+    grad_lap(G, (const T*)B.phi, x, y, z, phi, gphi, lapphi, true, C.stencil7 != 0);
+    grad_lap(G, mus, x, y, z, mu, gd, lapmu, false, C.stencil7 != 0);
     if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
     else flow_macro(C, g, phi, mu, gphi, lapmu, M);
   } else {
     T gr[3], lap;
-    grad_lap(G, (const T*)B.phi, x, y, z, phi, gr, lap, false);
+    grad_lap(G, (const T*)B.phi, x, y, z, phi, gr, lap, false, C.stencil7 != 0);
     M.phi = phi;
     M.mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
     M.rho = (1 + phi) / 2 * C.rho_l + (1 - phi) / 2 * C.rho_g;
@@ -351,6 +351,7 @@ Coef<T> cast_coef(const Coef<double>& c) {
   for (int i = 0; i < 7; ++i) o.sf[i] = (T)c.sf[i];
   for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
   o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
+  o.stencil7 = c.stencil7; o.forcing28 = c.forcing28;
   return o;
 }
 

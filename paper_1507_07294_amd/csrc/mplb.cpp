@@ -235,7 +235,20 @@ int mplb_set_params(mplb_t* h, const mplb_params* p) {
   C.rho_ref = p->rho_ref;
   for (int a = 0; a < 3; ++a) C.grav[a] = p->gravity[a];
   for (int i = 0; i < 7; ++i) C.sf[i] = p->s_f[i];
+  if ((p->stencil != MPLB_STENCIL_Q15 && p->stencil != MPLB_STENCIL_Q7) ||
+      (p->forcing != MPLB_FORCING_EQ32 && p->forcing != MPLB_FORCING_EQ28))
+    return fail(h, MPLB_E_INVAL, "unknown stencil or forcing switch");
+  C.stencil7 = p->stencil == MPLB_STENCIL_Q7;
+  C.forcing28 = p->forcing == MPLB_FORCING_EQ28;
+  if (C.forcing28 && h->mode == MPLB_COUPLED && h->prec != MPLB_F64 && h->prec != MPLB_F32)
+    return fail(h, MPLB_E_INVAL, "the Eq. 28 forcing is built for FP64 and FP32 storage");
   double tau_g = 3.0 * p->nu + 0.5;  // Eq. 33 with c_s^2 = 1/3
+  if (p->lambda_override) {          // the viscous rate itself is given
+    for (int i = 10; i <= 13; ++i)
+      if (p->lambda_g[i] != p->lambda_g[9]) return fail(h, MPLB_E_INVAL, "lambda_9..13 must be equal");
+    if (!in02(p->lambda_g[9])) return fail(h, MPLB_E_INVAL, "lambda[9] outside (0,2)");
+    tau_g = 1.0 / p->lambda_g[9];
+  }
   for (int i = 0; i < 15; ++i) C.lg[i] = (i >= 9 && i <= 13) ? 1.0 / tau_g : p->lambda_g[i];
   for (int i = 0; i < 15; ++i)
     if (!in02(C.lg[i])) return fail(h, MPLB_E_INVAL, "lambda[%d] outside (0,2)", i);
@@ -461,7 +474,10 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   }
   mplb_t* h0 = hs[0];
   hipStream_t s = h0->stream;
-  if (h0->mode != MPLB_COUPLED) {  // CHE-only and D3Q19 lattices step one after another on the stream
+  bool any_f28 = false;
+  for (int i = 0; i < count; ++i) any_f28 = any_f28 || hs[i]->C.forcing28;
+  // CHE-only, D3Q19 and untruncated-forcing lattices step one after another
+  if (h0->mode != MPLB_COUPLED || any_f28) {
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < count; ++i) {
         int rc = enqueue_step(hs[i], s);

@@ -39,7 +39,8 @@ class mplb_params(C.Structure):
     _fields_ = [("sigma", C.c_double), ("width", C.c_double), ("rho_l", C.c_double),
                 ("rho_g", C.c_double), ("mobility", C.c_double), ("A", C.c_double),
                 ("s_f", C.c_double * 7), ("nu", C.c_double), ("lambda_g", C.c_double * 15),
-                ("gravity", C.c_double * 3), ("rho_ref", C.c_double)]
+                ("gravity", C.c_double * 3), ("rho_ref", C.c_double),
+                ("stencil", C.c_int), ("forcing", C.c_int), ("lambda_override", C.c_int)]
 
 
 class MplbError(RuntimeError):
@@ -131,6 +132,9 @@ def to_params(p) -> mplb_params:
         o.lambda_g[i] = p.lambda_g[i]
     for a in range(3):
         o.gravity[a] = p.gravity[a]
+    o.stencil = int(getattr(p, "stencil", 0))
+    o.forcing = int(getattr(p, "forcing", 0))
+    o.lambda_override = int(getattr(p, "lambda_override", 0))
     return o
 
 

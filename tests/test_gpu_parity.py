@@ -119,6 +119,35 @@ def test_q19_totals_checkpoint_and_batch():
         assert np.array_equal(a.read(k), c.read(k)) and np.array_equal(b.read(k), c.read(k)), k
 
 
+@pytest.mark.parametrize("stencil,forcing,override", [(1, 0, 0), (0, 1, 0), (1, 1, 1)])
+def test_switches_f64(stencil, forcing, override):
+    """The study switches against the oracle (FP64): D3Q7 finite differences,
+    the untruncated Eq. 28 forcing, and lambda_9..13 given directly."""
+    w = wl.perturbed_case((24, 20, 18), (1, 0, 1), 61 + stencil + 2 * forcing, coupled=True, ratio=4.0)
+    lam = list(w.params.lambda_g)
+    lam[9:14] = [1.3] * 5
+    w.params = w.params.replace(stencil=stencil, forcing=forcing, lambda_override=override, lambda_g=tuple(lam))
+    _compare(w, [1, 10, 60], "f64", F64_TOL)
+
+
+def test_switches_che_only_and_16bit():
+    """D3Q7 stencil in the CHE-only step (FP64) and in the 16-bit coupled
+    step; the untruncated forcing is refused with 16-bit storage."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((30, 26, 22), (0, 0, 1), 64, coupled=False)
+    w.velocity = {"kind": "deformation", "U": 0.02, "T": 0.05}
+    w.params = w.params.replace(stencil=1)
+    _compare(w, [1, 7, 40], "f64", F64_TOL, coupled=False)
+    w2 = wl.perturbed_case((24, 20, 18), (0, 0, 1), 65, coupled=True)
+    w2.params = w2.params.replace(stencil=1)
+    _compare(w2, [1, 10, 60], "f16", 5e-3)
+    lt = mplb.Lattice(w2.shape, w2.bc, "f16", mplb.MPLB_COUPLED)
+    with pytest.raises(mplb.MplbError) as ei:
+        lt.set_params(w2.params.replace(forcing=1))
+    assert ei.value.code == mplb.MPLB_E_INVAL
+    lt.destroy()
+
+
 @pytest.mark.parametrize("kind", ["field", "zalesak", "deformation"])
 @pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
 def test_che_only(kind, precision, tol):
