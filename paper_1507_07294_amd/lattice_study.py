@@ -7,6 +7,8 @@ Sec. II B after Eq. 22): accuracy against throughput.
 * A Rayleigh-Taylor box (FP32): spike and bubble positions of the two
   lattices at the same times.
 * Throughput of the FP32 step on the 256 x 256 x 1024 Rayleigh-Taylor box.
+* The two study switches of the D3Q15 model on the 48^3 droplet: D3Q7 finite
+  differences, and the untruncated forcing of Eq. 28.
 
 One JSON line per result:
 
@@ -31,8 +33,9 @@ def _with_q(w, q):
     return w
 
 
-def laplace_run(q, n=48, R=12.0, steps=3000, sigma=0.01, D=4.0):
+def laplace_run(q, n=48, R=12.0, steps=3000, sigma=0.01, D=4.0, stencil=0, forcing=0):
     w = _with_q(wl.static_droplet(n=n, R=R, D=D, sigma=sigma), q)
+    w.params = w.params.replace(stencil=stencil, forcing=forcing)
     lt = mplb.from_workload(w, "f64")
     lt.step(steps)
     phi, p = lt.read("phi"), lt.read("p")
@@ -44,7 +47,8 @@ def laplace_run(q, n=48, R=12.0, steps=3000, sigma=0.01, D=4.0):
     R_eff = (3.0 * ((1.0 + phi) / 2.0).sum() / (4.0 * math.pi)) ** (1.0 / 3.0)
     dp = p[r < R_eff - D].mean() - p[r > R_eff + D].mean()
     ref = 2.0 * sigma / R_eff
-    return {"case": "laplace", "q": q, "n": n, "R": R, "steps": steps, "R_eff": round(R_eff, 4),
+    return {"case": "laplace", "q": q, "stencil": "D3Q7" if stencil else "D3Q15",
+            "forcing": "Eq. 28" if forcing else "Eq. 32", "n": n, "R": R, "steps": steps, "R_eff": round(R_eff, 4),
             "dp": float(f"{dp:.6e}"), "two_sigma_over_R": float(f"{ref:.6e}"),
             "laplace_rel_err": float(f"{abs(dp - ref) / ref:.4e}"), "max_spurious_u": float(f"{u.max():.4e}")}
 
@@ -89,6 +93,11 @@ def main(argv=None):
     for q in (15, 19):
         for n, R in ((32, 8.0), (48, 12.0)):
             print(json.dumps(laplace_run(q, n=n, R=R, steps=args.steps)), flush=True)
+    # the study switches on the D3Q15 model: finite differences on D3Q7, the
+    # untruncated forcing
+    for stencil, forcing in ((1, 0), (0, 1)):
+        print(json.dumps(laplace_run(15, n=48, R=12.0, steps=args.steps, stencil=stencil, forcing=forcing)),
+              flush=True)
     for row in front_run():
         print(json.dumps(row), flush=True)
     for q in (15, 19):
