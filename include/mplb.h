@@ -93,13 +93,13 @@ typedef struct mplb_params {
                           unless lambda_override */
   double gravity[3];   /* body acceleration; G = (rho - rho_ref) gravity */
   double rho_ref;      /* reference density of the body force (0: G = rho gravity) */
-  /* study switches; 0 selects the readings used by default */
+  /* study switches; 0 selects the readings used by default.  The switches are
+     built for FP64 and FP32 storage (mplb_set_params returns MPLB_E_INVAL for
+     16-bit storage), and mplb_step_many steps such lattices one after another. */
   int stencil;         /* MPLB_STENCIL_Q15: Eqs. 35-36 with the D3Q15 weights; MPLB_STENCIL_Q7: with the
                           D3Q7 weights (central differences and the 7-point Laplacian) */
   int forcing;         /* MPLB_FORCING_EQ32: the printed moments of Eq. 32; MPLB_FORCING_EQ28: Gamma T of
-                          Eq. 28 untruncated, FP64 and FP32 storage only (MPLB_E_INVAL otherwise); such
-                          lattices step one after another in mplb_step_many.  The D3Q19 variant always
-                          uses Gamma T. */
+                          Eq. 28 untruncated.  The D3Q19 variant always uses Gamma T. */
   int lambda_override; /* nonzero: lambda_9..13 are taken from lambda_g (all equal) instead of from nu */
 } mplb_params;
 

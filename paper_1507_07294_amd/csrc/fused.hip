@@ -395,6 +395,7 @@ struct MuMaker {
     }
   }
 
+  template <bool S7 = false>
   __device__ void run(const Geo& G, const Coef<typename Prec<P>::T>& C, int zl,
                       typename Prec<P>::T (*sphi)[R2::NPHI], typename Prec<P>::T* smu) {
     using T = typename Prec<P>::T;
@@ -406,7 +407,7 @@ struct MuMaker {
     for (int k = 0; k < MPT; ++k) {
       if (on[k]) {
         T c0 = pc[src[k]];
-        T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k], C.stencil7 != 0);
+        T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k], S7);
         smu[dst[k]] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
       }
     }
@@ -417,9 +418,14 @@ struct MuMaker {
 template <int P>
 constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
 
+// Study variants of a step kernel, compile-time so that the default kernels
+// carry no code for them: D3Q7 finite differences (Eqs. 35-36), and Gamma T
+// of Eq. 28 in place of the printed Eq. 32.  Built for FP64 and FP32 storage.
+constexpr int kVarS7 = 1, kVarF28 = 2;
+
 // The coupled step of logical block lb of one lattice (NT: streaming stores;
-// Q: velocities of the NSE lattice, 15 or 19).
-template <int P, int TY, bool XYWALL, bool NT, int Q = 15, bool F28 = false>
+// Q: velocities of the NSE lattice, 15 or 19; V: study variant bits).
+template <int P, int TY, bool XYWALL, bool NT, int Q = 15, int V = 0>
 __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                                   const Tiling& TL, int lb) {
   using T = typename Prec<P>::T;
@@ -459,8 +465,8 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   // warm-up: phi planes z0-2 .. z0+1, mu planes z0-1, z0
   for (int zl = z0 - 2; zl <= z0 + 1; ++zl) ld.load(G, fin, zl, sphi[(zl + 10) % 5], sfq[(zl + 9) % 3]);
   __syncthreads();
-  mm.run(G, C, z0 - 1, sphi, smu[(z0 - 1 + 6) % 3]);
-  mm.run(G, C, z0, sphi, smu[(z0 + 6) % 3]);
+  mm.template run<(V & kVarS7) != 0>(G, C, z0 - 1, sphi, smu[(z0 - 1 + 6) % 3]);
+  mm.template run<(V & kVarS7) != 0>(G, C, z0, sphi, smu[(z0 + 6) % 3]);
 
   for (int z = z0; z < z1; ++z) {
     const int zo = z * G.nx * G.ny;
@@ -476,7 +482,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5], sfq[(z + 2 + 9) % 3]);
     __syncthreads();
-    mm.run(G, C, z + 1, sphi, smu[(z + 1 + 6) % 3]);
+    mm.template run<(V & kVarS7) != 0>(G, C, z + 1, sphi, smu[(z + 1 + 6) % 3]);
     __syncthreads();
     if (!own) continue;
     const QT* q = sfq[(z + 9) % 3];
@@ -502,10 +508,10 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     T phi = phi_of(f);
     T gphi[3];
     grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi,
-                       C.stencil7 != 0);
+                       (V & kVarS7) != 0);
     const T* mc = smu[(z + 6) % 3];
     T mu = mc[mu_c];
-    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c, C.stencil7 != 0);
+    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c, (V & kVarS7) != 0);
     Macro<T> M;
     if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
     else flow_macro(C, g, phi, mu, gphi, lapmu, M);
@@ -519,7 +525,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
     if constexpr (Q == 19) collide_ns19(C, g, M);
-    else collide_ns<F28>(C, g, M);
+    else collide_ns<(V & kVarF28) != 0>(C, g, M);
     using S0 = typename L::S0;
     using S = typename L::S;
     st_at<NT>(L::f0(fo) + zo, col_xy, (S0)f[0]);
@@ -542,10 +548,10 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   }
 }
 
-template <int P, int TY, bool XYWALL, bool NT, int Q, bool F28 = false>
+template <int P, int TY, bool XYWALL, bool NT, int Q, int V = 0>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
-  fused_body<P, TY, XYWALL, NT, Q, F28>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
+  fused_body<P, TY, XYWALL, NT, Q, V>(G, C, B, cur, TL, logical_block(blockIdx.x, gridDim.x));
 }
 
 // Many lattices in one launch (continuous batching): the blocks of all
@@ -569,7 +575,7 @@ k_fused_many(const BatchItem<typename Prec<P>::T>* __restrict__ tab, int count, 
 
 // CHE-only: mu is needed at the node only, so phi needs a halo of one and a
 // ring of 4 planes (plane z+1 is loaded while plane z is finished).
-template <int P, int TY, bool XYWALL, bool NT>
+template <int P, int TY, bool XYWALL, bool NT, int V = 0>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using T = typename Prec<P>::T;
@@ -605,7 +611,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * R::NT + threadIdx.x];
     T phi = phi_of(f);
     T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c,
-                              C.stencil7 != 0);
+                              (V & kVarS7) != 0);
     T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
     T u[3], up[3];
     presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
@@ -666,37 +672,43 @@ Tiling make_tiling(const Geo& G, int TY, int min_lz) {
 // 18 % slower for a 128^3 CHE-only box that stays cache-resident).
 constexpr size_t kStreamBytes = (size_t)512 << 20;
 
-template <int P, bool XYWALL, bool NT>
-hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
+template <int P, bool XYWALL, bool NT, int V>
+hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s) {
-  if (mode == MPLB_COUPLED) {
+  if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
     Tiling tl = make_tiling(G, kTY, 16);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-    if (C.forcing28) {  // the untruncated forcing is built for FP64 and FP32 storage
-      if constexpr (P == MPLB_F64 || P == MPLB_F32)
-        hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15, true>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
-      else
-        return hipErrorInvalidValue;
-    } else {
-      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
-    }
-  } else if (mode == MPLB_COUPLED_Q19) {
-    // D3Q19 is built for FP64 and FP32 storage
-    if constexpr (P == MPLB_F64 || P == MPLB_F32) {
-      Tiling tl = make_tiling(G, kTY, 16);
-      dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 19>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
-    } else {
+    if (mode == MPLB_COUPLED)
+      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15, V>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    else if constexpr (P == MPLB_F64 || P == MPLB_F32)  // D3Q19: FP64 and FP32 storage; its forcing is Gamma T
+      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B,
+                         cur, tl);
+    else
       return hipErrorInvalidValue;
-    }
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
     Tiling tl = make_tiling(G, kTY, 8);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-    hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+    hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,
+                       tl);
   }
   return hipGetLastError();
+}
+
+template <int P, bool XYWALL, bool NT>
+hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
+                       hipStream_t s) {
+  const int v = (C.stencil7 ? kVarS7 : 0) | (C.forcing28 ? kVarF28 : 0);
+  if (v == 0) return fused_impl4<P, XYWALL, NT, 0>(mode, G, C, B, cur, s);
+  if constexpr (P == MPLB_F64 || P == MPLB_F32) {
+    switch (v) {
+      case kVarS7: return fused_impl4<P, XYWALL, NT, kVarS7>(mode, G, C, B, cur, s);
+      case kVarF28: return fused_impl4<P, XYWALL, NT, kVarF28>(mode, G, C, B, cur, s);
+      default: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28>(mode, G, C, B, cur, s);
+    }
+  }
+  return hipErrorInvalidValue;  // the study variants are built for FP64 and FP32 storage
 }
 
 template <int P, bool XYWALL>

@@ -240,8 +240,8 @@ int mplb_set_params(mplb_t* h, const mplb_params* p) {
     return fail(h, MPLB_E_INVAL, "unknown stencil or forcing switch");
   C.stencil7 = p->stencil == MPLB_STENCIL_Q7;
   C.forcing28 = p->forcing == MPLB_FORCING_EQ28;
-  if (C.forcing28 && h->mode == MPLB_COUPLED && h->prec != MPLB_F64 && h->prec != MPLB_F32)
-    return fail(h, MPLB_E_INVAL, "the Eq. 28 forcing is built for FP64 and FP32 storage");
+  if ((C.stencil7 || C.forcing28) && h->prec != MPLB_F64 && h->prec != MPLB_F32)
+    return fail(h, MPLB_E_INVAL, "the stencil and forcing switches are built for FP64 and FP32 storage");
   double tau_g = 3.0 * p->nu + 0.5;  // Eq. 33 with c_s^2 = 1/3
   if (p->lambda_override) {          // the viscous rate itself is given
     for (int i = 10; i <= 13; ++i)
@@ -474,10 +474,11 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   }
   mplb_t* h0 = hs[0];
   hipStream_t s = h0->stream;
-  bool any_f28 = false;
-  for (int i = 0; i < count; ++i) any_f28 = any_f28 || hs[i]->C.forcing28;
-  // CHE-only, D3Q19 and untruncated-forcing lattices step one after another
-  if (h0->mode != MPLB_COUPLED || any_f28) {
+  bool any_switch = false;
+  for (int i = 0; i < count; ++i) any_switch = any_switch || hs[i]->C.forcing28 || hs[i]->C.stencil7;
+  // CHE-only and D3Q19 lattices, and lattices with a study switch, step one
+  // after another (the batched kernel is the default D3Q15 step)
+  if (h0->mode != MPLB_COUPLED || any_switch) {
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < count; ++i) {
         int rc = enqueue_step(hs[i], s);

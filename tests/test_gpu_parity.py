@@ -131,8 +131,8 @@ def test_switches_f64(stencil, forcing, override):
 
 
 def test_switches_che_only_and_16bit():
-    """D3Q7 stencil in the CHE-only step (FP64) and in the 16-bit coupled
-    step; the untruncated forcing is refused with 16-bit storage."""
+    """D3Q7 stencil in the CHE-only step (FP64); the switches are refused with
+    16-bit storage (they are built for FP64 and FP32)."""
     from paper_1507_07294_amd import mplb
     w = wl.perturbed_case((30, 26, 22), (0, 0, 1), 64, coupled=False)
     w.velocity = {"kind": "deformation", "U": 0.02, "T": 0.05}
@@ -140,11 +140,12 @@ def test_switches_che_only_and_16bit():
     _compare(w, [1, 7, 40], "f64", F64_TOL, coupled=False)
     w2 = wl.perturbed_case((24, 20, 18), (0, 0, 1), 65, coupled=True)
     w2.params = w2.params.replace(stencil=1)
-    _compare(w2, [1, 10, 60], "f16", 5e-3)
+    _compare(w2, [1, 10, 60], "f32", F32_TOL)
     lt = mplb.Lattice(w2.shape, w2.bc, "f16", mplb.MPLB_COUPLED)
-    with pytest.raises(mplb.MplbError) as ei:
-        lt.set_params(w2.params.replace(forcing=1))
-    assert ei.value.code == mplb.MPLB_E_INVAL
+    for sw in ({"forcing": 1}, {"stencil": 1}):
+        with pytest.raises(mplb.MplbError) as ei:
+            lt.set_params(w2.params.replace(**{"stencil": 0, "forcing": 0, **sw}))
+        assert ei.value.code == mplb.MPLB_E_INVAL
     lt.destroy()
 
 
