@@ -53,6 +53,21 @@ def rel_errors(a, b):
     return {k: rel_err(a[k], b[k], FLOORS.get(k, 0.0)) for k in b}
 
 
+def mu_error_bound(params, dphi_rms, eps):
+    """Bound on the RMS error of mu = 4 beta (phi^3 - phi) - kappa lap phi
+    (Eqs. 2, 36) that a phi error of RMS dphi_rms, plus rounding at unit
+    round-off eps in the evaluation itself, can cause.  The double-well term
+    has slope 4 beta (3 phi^2 - 1) <= 8 beta for |phi| <= 1; the isotropic
+    Laplacian's stencil (weights 2 w_i / c_s^2) has an absolute coefficient
+    sum 12 (1 - w_0) <= 12, which bounds its L2 gain (Young's inequality).
+    The bound holds at any lattice size, where the relative L2 of mu does not:
+    mu vanishes in the bulk, so its norm grows with the interface area while
+    the round-off grows with the volume."""
+    beta = 3.0 * params.sigma / (4.0 * params.width)
+    kappa = 3.0 * params.width * params.sigma / 8.0
+    return (8.0 * beta + 12.0 * kappa) * dphi_rms + eps * (12.0 * beta + 12.0 * kappa)
+
+
 # ---------------------------------------------------------------------------
 # Windowed oracle: fields at sampled nodes of a lattice too large for the
 # oracle.  After n steps a node depends on the initial state within 3 hops
