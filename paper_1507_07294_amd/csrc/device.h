@@ -221,6 +221,44 @@ __device__ inline void presc_u(const Geo& G, const Coef<T>& C, const T* uf, int 
   if (up) up[0] = u[0], up[1] = u[1], up[2] = u[2];
 }
 
+// presc_u along one lattice column (x, y) of a z march: the deformation
+// flow (Eq. 41) is a product of x-y factors, evaluated once per column, and
+// z factors, evaluated once per plane; the products keep presc_u's order,
+// so the values are the same.
+template <class T>
+struct PrescColumn {
+  T a[3] = {0, 0, 0};  // 2U sx^2 s2y, -U s2x sy^2, -U s2x s2y
+
+  __device__ void init(const Geo& G, const Coef<T>& C, int x, int y) {
+    if (C.vel_kind != MPLB_VEL_DEFORM) return;
+    const T pi = (T)3.14159265358979323846;
+    T xh = (T)x / (T)G.nx, yh = (T)y / (T)G.ny;
+    T sx = sin(pi * xh), sy = sin(pi * yh);
+    T s2x = sin(2 * pi * xh), s2y = sin(2 * pi * yh);
+    T U = C.velU;
+    a[0] = 2 * U * sx * sx * s2y;
+    a[1] = -U * s2x * sy * sy;
+    a[2] = -U * s2x * s2y;
+  }
+
+  __device__ void at(const Geo& G, const Coef<T>& C, const T* uf, int x, int y, int z, int n, T u[3],
+                     T up[3]) const {
+    if (C.vel_kind != MPLB_VEL_DEFORM) {
+      presc_u(G, C, uf, x, y, z, n, u, up);
+      return;
+    }
+    const T pi = (T)3.14159265358979323846;
+    T zh = (T)z / (T)G.nz;
+    T sz = sin(pi * zh), s2z = sin(2 * pi * zh);
+    T b[3] = {a[0] * s2z, a[1] * s2z, a[2] * sz * sz};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      u[k] = b[k] * C.vel_ct;
+      up[k] = b[k] * C.vel_ct_prev;
+    }
+  }
+};
+
 // ------------------------------------------------------------ node physics
 // Macroscopic state of a node at level n (coupled model).
 template <class T>
@@ -244,19 +282,20 @@ __device__ inline void flow_macro(const Coef<T>& C, const T g[15], T phi, T mu, 
              (((g[7] + g[8]) + (g[9] + g[10])) + ((g[11] + g[12]) + (g[13] + g[14])));
   T Fs[3], Gb[3], j[3] = {jx, jy, jz};
   T ml = C.mob * lapmu;
-  T denom = m.rho - (T)0.25 * C.drho * ml;
+  // one division per node (a correctly rounded reciprocal) instead of three
+  const T inv = (T)1 / (m.rho - (T)0.25 * C.drho * ml);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     m.gr[a] = half_dr * gphi[a];
     Fs[a] = mu * gphi[a];
     Gb[a] = (m.rho - C.rho_ref) * C.grav[a];
-    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) / denom;
+    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) * inv;
     m.F[a] = Fs[a] + half_dr * ml * m.u[a] + Gb[a];
   }
   T uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
   T ugr = m.u[0] * m.gr[0] + m.u[1] * m.gr[1] + m.u[2] * m.gr[2];
   // c_s^2 / (1 - w_0) = 3/7 and rho s_0(u) = -rho |u|^2 / 3 (Eq. 30)
-  m.p = (T)(3.0 / 7.0) * (sum_nz + (T)0.5 * ugr - m.rho * uu / 3);
+  m.p = (T)(3.0 / 7.0) * (sum_nz + (T)0.5 * ugr - m.rho * uu * (T)(1.0 / 3.0));
 }
 
 // The same on D3Q19 (weights 1/3, 1/18, 1/36): c_s^2 / (1 - w_0) = 1/2 and
@@ -278,18 +317,19 @@ __device__ inline void flow_macro19(const Coef<T>& C, const T g[19], T phi, T mu
   }
   T Fs[3], Gb[3];
   T ml = C.mob * lapmu;
-  T denom = m.rho - (T)0.25 * C.drho * ml;
+  // one division per node (a correctly rounded reciprocal) instead of three
+  const T inv = (T)1 / (m.rho - (T)0.25 * C.drho * ml);
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     m.gr[a] = half_dr * gphi[a];
     Fs[a] = mu * gphi[a];
     Gb[a] = (m.rho - C.rho_ref) * C.grav[a];
-    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) / denom;
+    m.u[a] = (j[a] + (T)0.5 * (Fs[a] + Gb[a])) * inv;
     m.F[a] = Fs[a] + half_dr * ml * m.u[a] + Gb[a];
   }
   T uu = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
   T ugr = m.u[0] * m.gr[0] + m.u[1] * m.gr[1] + m.u[2] * m.gr[2];
-  m.p = (T)0.5 * (sum_nz + (T)0.5 * ugr - m.rho * uu / 2);
+  m.p = (T)0.5 * (sum_nz + (T)0.5 * ugr - (T)0.5 * m.rho * uu);
 }
 
 // D3Q7 collision in moment space (Eqs. 15, 17, 18, 11): m = M f;
@@ -367,11 +407,11 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
   eq[1] = 3 * p + rho * uu;
   eq[2] = -(45 * p + 5 * rho * uu);
   eq[3] = rho * u[0];
-  eq[4] = -7 * rho * u[0] / 3;
+  eq[4] = (T)(-7.0 / 3.0) * rho * u[0];
   eq[5] = rho * u[1];
-  eq[6] = -7 * rho * u[1] / 3;
+  eq[6] = (T)(-7.0 / 3.0) * rho * u[1];
   eq[7] = rho * u[2];
-  eq[8] = -7 * rho * u[2] / 3;
+  eq[8] = (T)(-7.0 / 3.0) * rho * u[2];
   eq[9] = rho * (2 * u[0] * u[0] - u[1] * u[1] - u[2] * u[2]);
   eq[10] = rho * (u[1] * u[1] - u[2] * u[2]);
   eq[11] = rho * u[0] * u[1];
@@ -387,11 +427,11 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
   src[1] = -ugr * cs2 + 2 * uF;
   src[2] = -(7 * ugr * cs2 + 10 * uF);
   src[3] = F[0];
-  src[4] = -7 * F[0] / 3;
+  src[4] = (T)(-7.0 / 3.0) * F[0];
   src[5] = F[1];
-  src[6] = -7 * F[1] / 3;
+  src[6] = (T)(-7.0 / 3.0) * F[1];
   src[7] = F[2];
-  src[8] = -7 * F[2] / 3;
+  src[8] = (T)(-7.0 / 3.0) * F[2];
   src[9] = 4 * u[0] * a[0] - 2 * u[1] * a[1] - 2 * u[2] * a[2];
   src[10] = 2 * u[1] * a[1] - 2 * u[2] * a[2];
   src[11] = u[0] * a[1] + u[1] * a[0];

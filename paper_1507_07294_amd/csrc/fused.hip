@@ -159,39 +159,49 @@ __device__ inline void st_at(S* base, int xy, S v) {
 }
 
 // The seven f of the node at in-plane index xy of the plane p (plane offset
-// zo).  PACK: the words of f_1..f_6 carry g_1..g_6 in their high halves;
-// they are returned raw in w (when w is given).
-template <int P, bool PACK, bool XYWALL>
-__device__ inline void pull_f7(const Geo& G, const void* fb, const Column& c, const Plane& p, int zo, int xy,
-                               typename Prec<P>::T f[7], uint32_t* w) {
+// zo), as stored: f_0 in r0, f_1..f_6 in r (PACK: 32-bit words that carry
+// g_1..g_6 in their high halves).
+template <int P, bool PACK>
+struct F7Raw {
   using L = Lat<P, PACK>;
-  using T = typename Prec<P>::T;
-  using S0 = typename L::S0;
   using QS = typename std::conditional<PACK, uint32_t, typename L::S>::type;
-  f[0] = (T)ld_at(L::f0(fb) + zo, xy);
+  typename L::S0 r0;
+  QS r[6];
+};
+
+template <int P, bool PACK, bool XYWALL>
+__device__ inline void pull_f7_raw(const Geo& G, const void* fb, const Column& c, const Plane& p, int zo, int xy,
+                                   F7Raw<P, PACK>& o) {
+  using L = Lat<P, PACK>;
+  using QS = typename F7Raw<P, PACK>::QS;
+  o.r0 = ld_at(L::f0(fb) + zo, xy);
   const QS* fi = (const QS*)L::fi(fb, G.pitch);
 #pragma unroll
   for (int i = 1; i < 7; ++i) {
     const int cx = c7(i, 0), cy = c7(i, 1), cz = c7(i, 2);
-    QS v;
     if constexpr (XYWALL) {
       const bool b = bounced<XYWALL>(c, p, cx, cy, cz);
       const int idx = b ? zo + xy : source(c, p, cx, cy, cz);
-      v = fi[(size_t)((b ? opp(i) : i) - 1) * G.pitch + idx];
+      o.r[i - 1] = fi[(size_t)((b ? opp(i) : i) - 1) * G.pitch + idx];
     } else {
       // z-wall bounce is uniform: pick array and plane on the scalar side
       const bool b = p.zb[cz + 1];
       const QS* base = plane_base<QS>(fi, (size_t)((b ? opp(i) : i) - 1), G.pitch, b ? zo : p.zs[cz + 1]);
-      v = ld_at(base, b ? xy : c.ys[cy + 1] + c.xs[cx + 1]);
-    }
-    if constexpr (PACK) {
-      f[i] = L::lo(v);
-      if (w) w[i - 1] = v;
-    } else {
-      f[i] = (T)v;
+      o.r[i - 1] = ld_at(base, b ? xy : c.ys[cy + 1] + c.xs[cx + 1]);
     }
   }
-  (void)sizeof(S0);
+}
+
+template <int P, bool PACK>
+__device__ inline void cvt_f7(const F7Raw<P, PACK>& o, typename Prec<P>::T f[7]) {
+  using L = Lat<P, PACK>;
+  using T = typename Prec<P>::T;
+  f[0] = (T)o.r0;
+#pragma unroll
+  for (int i = 1; i < 7; ++i) {
+    if constexpr (PACK) f[i] = L::lo(o.r[i - 1]);
+    else f[i] = (T)o.r[i - 1];
+  }
 }
 
 // Raw pulls of the g (storage type, no conversion), issued ahead of the
@@ -342,20 +352,28 @@ struct PhiLoader {
   }
 
   // phi of logical plane zl (mapped onto the lattice) into ring slot s; the
-  // own node's pulled populations go to q[i * NT + thread] when q is given
+  // own node's pulled populations go to q[i * NT + thread] when q is given.
+  // Every pull of the plane (own node and halo) is issued before the first
+  // value is used, so that the wave waits for memory once per plane; a
+  // thread without a halo position pulls a valid node (its column was set up
+  // from the tile corner) and drops the value.
   __device__ void load(const Geo& G, const void* fin, int zl, T* s, QT* q = nullptr) {
     int mz = map_axis(zl, G.nz, G.wall_z);
     Plane p = make_plane(G, mz);
     int zo = mz * G.nx * G.ny;
+    F7Raw<P, PACK> ro, rh[R::HPT];
+    pull_f7_raw<P, PACK, XYWALL>(G, fin, own, p, zo, own_xy, ro);
+#pragma unroll
+    for (int k = 0; k < R::HPT; ++k) pull_f7_raw<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], rh[k]);
+    __builtin_amdgcn_sched_barrier(0);
     T f[7];
-    uint32_t w[6];
-    pull_f7<P, PACK, XYWALL>(G, fin, own, p, zo, own_xy, f, w);
+    cvt_f7<P, PACK>(ro, f);
     s[own_lds] = phi_of(f);
     if (q) {
       if constexpr (PACK) {
         q[threadIdx.x] = __builtin_bit_cast(uint32_t, (float)f[0]);
 #pragma unroll
-        for (int i = 1; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)w[i - 1];
+        for (int i = 1; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)ro.r[i - 1];
       } else {
 #pragma unroll
         for (int i = 0; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)f[i];
@@ -363,10 +381,9 @@ struct PhiLoader {
     }
 #pragma unroll
     for (int k = 0; k < R::HPT; ++k) {
-      if (halo_on[k]) {
-        pull_f7<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], f, nullptr);
-        s[halo_lds[k]] = phi_of(f);
-      }
+      T fh[7];
+      cvt_f7<P, PACK>(rh[k], fh);
+      if (halo_on[k]) s[halo_lds[k]] = phi_of(fh);
     }
   }
 };
@@ -472,13 +489,19 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     const int zo = z * G.nx * G.ny;
     const Plane p = make_plane(G, z);
     T f[7], g[Q];
-    // 16-bit storage: the node's g pulls go out before the phi and mu stages,
-    // so that their latency overlaps those of the phi pulls (measured 2.03 ->
-    // 1.98 ms per step at 256 x 256 x 1024; at 32 and 64 bits the registers
-    // they hold cost more than they save)
+    // 16-bit storage: the node's g pulls and (phi u) history loads go out
+    // before the phi and mu stages, so that their latency overlaps those of
+    // the phi pulls (measured 2.03 -> 1.98 ms per step at 256 x 256 x 1024
+    // for the g pulls; at 32 and 64 bits the registers they hold cost more
+    // than they save)
     typename L::S graw[Q];
+    T hprev[3];
     if constexpr (PACK) {
-      if (own) pull_gq_raw<P, PACK, XYWALL, Q>(G, gin, col, p, zo, col_xy, graw);
+      if (own) {
+        pull_gq_raw<P, PACK, XYWALL, Q>(G, gin, col, p, zo, col_xy, graw);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) hprev[a] = ld_at(hist + ((size_t)a * G.pitch + zo), col_xy);
+      }
     }
     ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5], sfq[(z + 2 + 9) % 3]);
     __syncthreads();
@@ -520,7 +543,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     for (int a = 0; a < 3; ++a) {
       T pu = phi * M.u[a];
       T* h = hist + ((size_t)a * G.pitch + zo);
-      dphiu[a] = pu - ld_at(h, col_xy);
+      dphiu[a] = pu - (PACK ? hprev[a] : ld_at(h, col_xy));
       st_at<NT>(h, col_xy, pu);
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
@@ -598,6 +621,8 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
   const int col_xy = gx + G.nx * gy;
   const int lds_c = (ty + 1) * R::PX + tx + 1;
+  PrescColumn<T> pc;
+  pc.init(G, C, gx, gy);
   ld.load(G, fin, z0 - 1, sphi[(z0 - 1 + 8) % 4]);
   ld.load(G, fin, z0, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
   for (int z = z0; z < z1; ++z) {
@@ -614,7 +639,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
                               (V & kVarS7) != 0);
     T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
     T u[3], up[3];
-    presc_u(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
+    pc.at(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
     // Eq. 34 with u known at both levels: only phi of the previous level is kept
     const T phip = ld_at(hist + zo, col_xy);
     st_at<NT>(hist + zo, col_xy, phi);
