@@ -85,8 +85,11 @@ struct Lat {
   // 16-bit halves <-> compute type
   __device__ static T lo(uint32_t w) { return (T)__builtin_bit_cast(S, (uint16_t)(w & 0xffffu)); }
   __device__ static T hi(uint32_t w) { return (T)__builtin_bit_cast(S, (uint16_t)(w >> 16)); }
+  // one packed conversion for both halves (round to nearest even)
   __device__ static uint32_t pack(T a, T b) {
-    return (uint32_t)__builtin_bit_cast(uint16_t, (S)a) | ((uint32_t)__builtin_bit_cast(uint16_t, (S)b) << 16);
+    typedef float F2 __attribute__((ext_vector_type(2)));
+    typedef S S2 __attribute__((ext_vector_type(2)));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((F2){(float)a, (float)b}, S2));
   }
 };
 

@@ -4,19 +4,23 @@
 //
 // A block owns a 64 x TY column of nodes and marches along z through a
 // segment [z0, z1).  At plane z it
-//   (a) pulls the seven f populations of plane z+2 on the tile plus a halo of
-//       two nodes and sums them into phi (Eq. 13) in an LDS ring of 5 planes,
-//   (b) evaluates mu (Eqs. 2, 36) of plane z+1 on the tile plus a halo of one
-//       into an LDS ring of 3 planes,
-//   (c) finishes the nodes of plane z: grad phi and lap mu (Eqs. 35-36) from
-//       LDS, pulls f and g, forms u, p and the forces (Eqs. 29-30),
-//       d_t(phi u) (Eq. 34), collides both lattices in moment space and
-//       stores f*, g* and (phi u).
-// Each stored population is pulled from HBM once, by the tile that owns its
-// destination: the tile's own f, pulled in (a), wait two planes in an LDS
-// queue (thread-private slots) for (c).  Only the halo pulls of (a) re-read
-// data, which blocks running together on one XCD share through its L2 (the
-// block order is remapped so that each XCD gets a contiguous run of tiles).
+//   (a) issues the pulls of the seven f populations of plane z+3 on the tile
+//       plus a halo of two nodes,
+//   (b) while they are in flight, evaluates mu (Eqs. 2, 36) of plane z+1 on
+//       the tile plus a halo of one into an LDS ring of 4 planes, then sums
+//       the pulled f into phi (Eq. 13) in an LDS ring of 6 planes,
+//   (c) after the one barrier of the plane, finishes the nodes of plane z:
+//       grad phi and lap mu (Eqs. 35-36) from LDS, pulls g, forms u, p and
+//       the forces (Eqs. 29-30), d_t(phi u) (Eq. 34), collides both lattices
+//       in moment space and stores f*, g* and (phi u).
+// The rings are deep enough that threads one barrier apart never touch the
+// same slot.  (The D3Q19 variant pulls plane z+2 instead and puts a second
+// barrier between (a) and (b).)  Each stored population is pulled from HBM once, by the tile
+// that owns its destination: the tile's own f, pulled in (a), wait three
+// planes in an LDS queue (thread-private slots) for (c).  Only the halo
+// pulls of (a) re-read data, which blocks running together on one XCD share
+// through its L2 (the block order is remapped so that each XCD gets a
+// contiguous run of tiles).
 //
 // Index arithmetic is hoisted out of the z loop: a thread's x and y source
 // offsets (with periodic wrap) are fixed for the whole march, and the plane
@@ -351,29 +355,32 @@ struct PhiLoader {
     }
   }
 
-  // phi of logical plane zl (mapped onto the lattice) into ring slot s; the
-  // own node's pulled populations go to q[i * NT + thread] when q is given.
-  // Every pull of the plane (own node and halo) is issued before the first
-  // value is used, so that the wave waits for memory once per plane; a
-  // thread without a halo position pulls a valid node (its column was set up
-  // from the tile corner) and drops the value.
-  __device__ void load(const Geo& G, const void* fin, int zl, T* s, QT* q = nullptr) {
+  // The pulls of logical plane zl (mapped onto the lattice), own node and
+  // halo, issued together so that the wave waits for memory once per plane;
+  // a thread without a halo position pulls a valid node (its column was set
+  // up from the tile corner) and drops the value.
+  struct Pending {
+    F7Raw<P, PACK> own, halo[R::HPT];
+  };
+  __device__ void issue(const Geo& G, const void* fin, int zl, Pending& pd) {
     int mz = map_axis(zl, G.nz, G.wall_z);
     Plane p = make_plane(G, mz);
     int zo = mz * G.nx * G.ny;
-    F7Raw<P, PACK> ro, rh[R::HPT];
-    pull_f7_raw<P, PACK, XYWALL>(G, fin, own, p, zo, own_xy, ro);
+    pull_f7_raw<P, PACK, XYWALL>(G, fin, own, p, zo, own_xy, pd.own);
 #pragma unroll
-    for (int k = 0; k < R::HPT; ++k) pull_f7_raw<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], rh[k]);
-    __builtin_amdgcn_sched_barrier(0);
+    for (int k = 0; k < R::HPT; ++k) pull_f7_raw<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], pd.halo[k]);
+  }
+  // phi of the pulled plane into ring slot s; the own node's populations go
+  // to q[i * NT + thread] when q is given
+  __device__ void finish(const Pending& pd, T* s, QT* q) {
     T f[7];
-    cvt_f7<P, PACK>(ro, f);
+    cvt_f7<P, PACK>(pd.own, f);
     s[own_lds] = phi_of(f);
     if (q) {
       if constexpr (PACK) {
         q[threadIdx.x] = __builtin_bit_cast(uint32_t, (float)f[0]);
 #pragma unroll
-        for (int i = 1; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)ro.r[i - 1];
+        for (int i = 1; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)pd.own.r[i - 1];
       } else {
 #pragma unroll
         for (int i = 0; i < 7; ++i) q[i * R::NT + threadIdx.x] = (QT)f[i];
@@ -382,9 +389,15 @@ struct PhiLoader {
 #pragma unroll
     for (int k = 0; k < R::HPT; ++k) {
       T fh[7];
-      cvt_f7<P, PACK>(rh[k], fh);
+      cvt_f7<P, PACK>(pd.halo[k], fh);
       if (halo_on[k]) s[halo_lds[k]] = phi_of(fh);
     }
+  }
+  __device__ void load(const Geo& G, const void* fin, int zl, T* s, QT* q = nullptr) {
+    Pending pd;
+    issue(G, fin, zl, pd);
+    __builtin_amdgcn_sched_barrier(0);
+    finish(pd, s, q);
   }
 };
 
@@ -395,7 +408,6 @@ struct MuMaker {
   static constexpr int QX = kTX + 2, QY = TY + 2, NMU = QX * QY;
   static constexpr int MPT = (NMU + R2::NT - 1) / R2::NT;
   int src[MPT];  // phi ring slot index of the position (or its mirror)
-  int dst[MPT];
   bool on[MPT];
 
   __device__ void init(const Geo& G, int x0, int y0) {
@@ -408,24 +420,25 @@ struct MuMaker {
       if (G.wall_x) gx = clamp_axis(gx, G.nx);
       if (G.wall_y) gy = clamp_axis(gy, G.ny);
       src[k] = (gy - (y0 - 2)) * R2::PX + (gx - (x0 - 2));
-      dst[k] = q;
     }
   }
 
-  template <bool S7 = false>
+  // mu of logical plane zl >= -1 into smu, from a phi ring of NR slots
+  // (plane z in slot (z + 2 NR) % NR)
+  template <int NR, bool S7 = false>
   __device__ void run(const Geo& G, const Coef<typename Prec<P>::T>& C, int zl,
                       typename Prec<P>::T (*sphi)[R2::NPHI], typename Prec<P>::T* smu) {
     using T = typename Prec<P>::T;
     int ze = G.wall_z ? clamp_axis(zl, G.nz) : zl;
-    const T* pm = sphi[(ze - 1 + 10) % 5];
-    const T* pc = sphi[(ze + 10) % 5];
-    const T* pp = sphi[(ze + 1 + 10) % 5];
+    const T* pm = sphi[(ze - 1 + 2 * NR) % NR];
+    const T* pc = sphi[(ze + 2 * NR) % NR];
+    const T* pp = sphi[(ze + 1 + 2 * NR) % NR];
 #pragma unroll
     for (int k = 0; k < MPT; ++k) {
       if (on[k]) {
         T c0 = pc[src[k]];
         T lap = lap_lds<T, R2::PX>(pm, pc, pp, src[k], S7);
-        smu[dst[k]] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
+        smu[threadIdx.x + k * R2::NT] = 4 * C.beta * c0 * (c0 - 1) * (c0 + 1) - C.kappa * lap;
       }
     }
   }
@@ -452,10 +465,16 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   using L = Lat<P, PACK>;
   using LD = PhiLoader<P, TY, 2, XYWALL, PACK>;
   using QT = typename LD::QT;
-  __shared__ T sphi[5][R::NPHI];
-  __shared__ T smu[3][MU::NMU];
-  // the own node's pulled populations of planes z, z+1, z+2 (thread-private slots)
+  // rings: phi of planes z-2 .. z+3, mu of planes z-2 .. z+1 (at most one
+  // barrier apart, threads read and write disjoint slots), and the own
+  // node's pulled populations of planes z .. z+2 (thread-private slots)
+  constexpr int NPR = 6, NMR = 4;
+  __shared__ T sphi[NPR][R::NPHI];
+  __shared__ T smu[NMR][MU::NMU];
   __shared__ QT sfq[3][7 * R::NT];
+  auto ps = [](int z) { return (z + 2 * NPR) % NPR; };  // z >= -2
+  auto ms = [](int z) { return (z + 2 * NMR) % NMR; };  // z >= -2
+  auto qs = [](int z) { return (z + 9) % 3; };
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
   const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
@@ -474,16 +493,27 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   ld.init(G, x0, y0);
   MU mm;
   mm.init(G, x0, y0);
-  const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
-  const int col_xy = gx + G.nx * gy;
-  const int lds_c = (ty + 2) * R::PX + tx + 2;
+  // the loader's own column is the node's column for every thread that owns a
+  // node (in-plane index gx + nx gy, ring position of the tile node)
+  const Column& col = ld.own;
+  const int col_xy = ld.own_xy;
+  const int lds_c = ld.own_lds;
   const int mu_c = (ty + 1) * MU::QX + tx + 1;
 
-  // warm-up: phi planes z0-2 .. z0+1, mu planes z0-1, z0
-  for (int zl = z0 - 2; zl <= z0 + 1; ++zl) ld.load(G, fin, zl, sphi[(zl + 10) % 5], sfq[(zl + 9) % 3]);
+  // The march issues the pulls of plane z+3 before mu of plane z+1 and has
+  // one barrier per plane (ONEBAR), or pulls plane z+2 and has a barrier
+  // after the pulls and after mu.  Measured at 256 x 256 x 1024: one barrier
+  // is 2 % faster for FP64 and 16-bit storage, no different for FP32, and
+  // 3 % slower for the D3Q19 lattice.
+  constexpr bool ONEBAR = Q == 15;
+  // warm-up: phi planes z0-2 .. z0+2 (ONEBAR) or z0+1 with the own
+  // populations of z0 on, mu planes z0-1, z0 (read after the first barrier
+  // of the march)
+  for (int zl = z0 - 2; zl <= z0 + (ONEBAR ? 2 : 1); ++zl)
+    ld.load(G, fin, zl, sphi[ps(zl)], zl >= z0 ? sfq[qs(zl)] : nullptr);
   __syncthreads();
-  mm.template run<(V & kVarS7) != 0>(G, C, z0 - 1, sphi, smu[(z0 - 1 + 6) % 3]);
-  mm.template run<(V & kVarS7) != 0>(G, C, z0, sphi, smu[(z0 + 6) % 3]);
+  mm.template run<NPR, (V & kVarS7) != 0>(G, C, z0 - 1, sphi, smu[ms(z0 - 1)]);
+  mm.template run<NPR, (V & kVarS7) != 0>(G, C, z0, sphi, smu[ms(z0)]);
 
   for (int z = z0; z < z1; ++z) {
     const int zo = z * G.nx * G.ny;
@@ -503,23 +533,41 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
         for (int a = 0; a < 3; ++a) hprev[a] = ld_at(hist + ((size_t)a * G.pitch + zo), col_xy);
       }
     }
-    ld.load(G, fin, z + 2, sphi[(z + 2 + 10) % 5], sfq[(z + 2 + 9) % 3]);
-    __syncthreads();
-    mm.template run<(V & kVarS7) != 0>(G, C, z + 1, sphi, smu[(z + 1 + 6) % 3]);
-    __syncthreads();
+    QT qv[7];
+    if constexpr (ONEBAR) {
+      // the own populations of plane z leave their queue slot, which plane
+      // z+3 takes over below
+#pragma unroll
+      for (int i = 0; i < 7; ++i) qv[i] = sfq[qs(z)][i * R::NT + threadIdx.x];
+      // the pulls of plane z+3 are in flight while mu of plane z+1 is formed
+      // (the last plane of the segment needs none: phi is read up to z1+1)
+      const bool more = z + 1 < z1;
+      typename LD::Pending pd;
+      if (more) ld.issue(G, fin, z + 3, pd);
+      __builtin_amdgcn_sched_barrier(0);
+      mm.template run<NPR, (V & kVarS7) != 0>(G, C, z + 1, sphi, smu[ms(z + 1)]);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) ld.finish(pd, sphi[ps(z + 3)], sfq[qs(z + 3)]);
+      __syncthreads();
+    } else {
+      ld.load(G, fin, z + 2, sphi[ps(z + 2)], sfq[qs(z + 2)]);
+      __syncthreads();
+      mm.template run<NPR, (V & kVarS7) != 0>(G, C, z + 1, sphi, smu[ms(z + 1)]);
+      __syncthreads();
+#pragma unroll
+      for (int i = 0; i < 7; ++i) qv[i] = sfq[qs(z)][i * R::NT + threadIdx.x];
+    }
     if (!own) continue;
-    const QT* q = sfq[(z + 9) % 3];
     if constexpr (PACK) {
-      f[0] = (T)__builtin_bit_cast(float, (uint32_t)q[threadIdx.x]);
+      f[0] = (T)__builtin_bit_cast(float, (uint32_t)qv[0]);
 #pragma unroll
       for (int i = 1; i < 7; ++i) {
-        const uint32_t w = (uint32_t)q[i * R::NT + threadIdx.x];
-        f[i] = L::lo(w);
-        g[i] = L::hi(w);
+        f[i] = L::lo((uint32_t)qv[i]);
+        g[i] = L::hi((uint32_t)qv[i]);
       }
     } else {
 #pragma unroll
-      for (int i = 0; i < 7; ++i) f[i] = (T)q[i * R::NT + threadIdx.x];
+      for (int i = 0; i < 7; ++i) f[i] = (T)qv[i];
     }
     if constexpr (PACK) {
       g[0] = (T)graw[0];
@@ -530,11 +578,10 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     T phi = phi_of(f);
     T gphi[3];
-    grad_lds<T, R::PX>(sphi[(z - 1 + 10) % 5], sphi[(z + 10) % 5], sphi[(z + 1 + 10) % 5], lds_c, gphi,
-                       (V & kVarS7) != 0);
-    const T* mc = smu[(z + 6) % 3];
+    grad_lds<T, R::PX>(sphi[ps(z - 1)], sphi[ps(z)], sphi[ps(z + 1)], lds_c, gphi, (V & kVarS7) != 0);
+    const T* mc = smu[ms(z)];
     T mu = mc[mu_c];
-    T lapmu = lap_lds<T, MU::QX>(smu[(z - 1 + 6) % 3], mc, smu[(z + 1 + 6) % 3], mu_c, (V & kVarS7) != 0);
+    T lapmu = lap_lds<T, MU::QX>(smu[ms(z - 1)], mc, smu[ms(z + 1)], mu_c, (V & kVarS7) != 0);
     Macro<T> M;
     if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
     else flow_macro(C, g, phi, mu, gphi, lapmu, M);
@@ -618,7 +665,6 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   T* hist = (T*)B.phiu;
   PhiLoader<P, TY, 1, XYWALL, false> ld;
   ld.init(G, x0, y0);
-  const Column col = make_column<XYWALL>(G, own ? gx : 0, own ? gy : 0);
   const int col_xy = gx + G.nx * gy;
   const int lds_c = (ty + 1) * R::PX + tx + 1;
   PrescColumn<T> pc;
