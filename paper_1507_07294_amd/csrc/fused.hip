@@ -644,13 +644,17 @@ k_fused_many(const BatchItem<typename Prec<P>::T>* __restrict__ tab, int count, 
 }
 
 // CHE-only: mu is needed at the node only, so phi needs a halo of one and a
-// ring of 4 planes (plane z+1 is loaded while plane z is finished).
+// ring of 4 planes.  At plane z the pulls of plane z+2 are issued, plane z is
+// finished while they are in flight, and their phi goes into the ring before
+// the one barrier of the plane (threads read planes z-1 .. z+1 and write
+// z+2, distinct slots).
 template <int P, int TY, bool XYWALL, bool NT, int V = 0>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 1>;
   using L = Lat<P, false>;
+  using LD = PhiLoader<P, TY, 1, XYWALL, false>;
   __shared__ T sphi[4][R::NPHI];
   __shared__ T sfq[2][7 * R::NT];  // the own node's pulled f of planes z, z+1
   const int lb = logical_block(blockIdx.x, gridDim.x);
@@ -663,7 +667,7 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const void* fin = B.f[cur];
   void* fo = B.f[1 - cur];
   T* hist = (T*)B.phiu;
-  PhiLoader<P, TY, 1, XYWALL, false> ld;
+  LD ld;
   ld.init(G, x0, y0);
   const int col_xy = gx + G.nx * gy;
   const int lds_c = (ty + 1) * R::PX + tx + 1;
@@ -671,36 +675,54 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   pc.init(G, C, gx, gy);
   ld.load(G, fin, z0 - 1, sphi[(z0 - 1 + 8) % 4]);
   ld.load(G, fin, z0, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
-  for (int z = z0; z < z1; ++z) {
-    ld.load(G, fin, z + 1, sphi[(z + 1 + 8) % 4], sfq[(z + 1) % 2]);
-    __syncthreads();
-    if (!own) continue;
+  ld.load(G, fin, z0 + 1, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
+  __syncthreads();
+  // plane z; PULL: also the pulls of plane z+2, which every plane but the
+  // last issues (phi is read up to plane z1, the Laplacian of plane z1-1).
+  // The last plane is a separate instantiation, so that no branch around the
+  // pulls leaves the compiler unsure how many loads are in flight.
+  auto plane = [&](int z, auto pull) {
+    constexpr bool PULL = decltype(pull)::value;
+    // phi of the previous level first: the memory counter retires in order,
+    // so a load issued after the pulls would wait for all of them
     const int zo = z * G.nx * G.ny;
-    const int n = zo + col_xy;
-    T f[7];
+    const T phip = own ? ld_at(hist + zo, col_xy) : (T)0;
+    typename LD::Pending pd;
+    if constexpr (PULL) ld.issue(G, fin, z + 2, pd);
+    __builtin_amdgcn_sched_barrier(0);
+    if (own) {
+      const int n = zo + col_xy;
+      T f[7];
 #pragma unroll
-    for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * R::NT + threadIdx.x];
-    T phi = phi_of(f);
-    T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c,
-                              (V & kVarS7) != 0);
-    T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
-    T u[3], up[3];
-    pc.at(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
-    // Eq. 34 with u known at both levels: only phi of the previous level is kept
-    const T phip = ld_at(hist + zo, col_xy);
-    st_at<NT>(hist + zo, col_xy, phi);
-    T dphiu[3];
+      for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * R::NT + threadIdx.x];
+      T phi = phi_of(f);
+      T lap = lap_lds<T, R::PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], lds_c,
+                                (V & kVarS7) != 0);
+      T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
+      T u[3], up[3];
+      pc.at(G, C, (const T*)B.ufield, gx, gy, z, n, u, up);
+      // Eq. 34 with u known at both levels: only phi of the previous level is kept
+      st_at<NT>(hist + zo, col_xy, phi);
+      T dphiu[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) dphiu[a] = phi * u[a] - phip * up[a];
-    collide_che(C, f, phi, mu, u, dphiu);
-    using S0 = typename L::S0;
-    using S = typename L::S;
-    st_at<NT>(L::f0(fo) + zo, col_xy, (S0)f[0]);
-    S* fa = L::fi(fo, G.pitch);
+      for (int a = 0; a < 3; ++a) dphiu[a] = phi * u[a] - phip * up[a];
+      collide_che(C, f, phi, mu, u, dphiu);
+      using S0 = typename L::S0;
+      using S = typename L::S;
+      st_at<NT>(L::f0(fo) + zo, col_xy, (S0)f[0]);
+      S* fa = L::fi(fo, G.pitch);
 #pragma unroll
-    for (int i = 1; i < 7; ++i) st_at<NT>(fa + ((size_t)(i - 1) * G.pitch + zo), col_xy, (S)f[i]);
-    if (!all_finite(f, 7)) *B.flag = 1;
-  }
+      for (int i = 1; i < 7; ++i) st_at<NT>(fa + ((size_t)(i - 1) * G.pitch + zo), col_xy, (S)f[i]);
+      if (!all_finite(f, 7)) *B.flag = 1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PULL) {
+      ld.finish(pd, sphi[(z + 2 + 8) % 4], sfq[z % 2]);
+      __syncthreads();
+    }
+  };
+  for (int z = z0; z < z1 - 1; ++z) plane(z, std::true_type{});
+  plane(z1 - 1, std::false_type{});
 }
 
 template <class T>
