@@ -33,8 +33,8 @@ CHE_ALGO_BYTES = {"f64": 2 * 8 * 8, "f32": 2 * 4 * 8}  # 7 populations + phi of 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--W", type=int, default=256, help="Rayleigh-Taylor box width (box W x W x 4W)")
     ap.add_argument("--variants", default="f16,bf16,f64", help="extra storage precisions to time ('' for none)")
     ap.add_argument("--no-che", action="store_true", help="skip the CHE-only interface-tracking line")
@@ -202,14 +202,16 @@ def main():
         torch.cuda.empty_cache()
 
     if args.copy_probe:
-        # bandwidth reference: the library's 16-byte streaming copy, and the
-        # runtime's own device copy, each over 4 GiB
+        # bandwidth reference: the library's 16-byte copies (plain, streaming
+        # stores, and four elements per thread with streaming loads and
+        # stores) and the runtime's own device copy, each over 4 GiB
         nbytes = 4 << 30
         a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
         b = torch.empty_like(a)
         probe = {}
         for name, fn in (("mplb_copy_probe", lambda: mplb.mplb_copy_probe(a, b, nbytes)),
-                         ("mplb_copy_probe_streaming", lambda: mplb.mplb_copy_probe(a, b, nbytes, True)),
+                         ("mplb_copy_probe_streaming", lambda: mplb.mplb_copy_probe(a, b, nbytes, 1)),
+                         ("mplb_copy_probe_x4", lambda: mplb.mplb_copy_probe(a, b, nbytes, 2)),
                          ("torch_copy", lambda: b.copy_(a))):
             for _ in range(3):
                 fn()

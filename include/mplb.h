@@ -209,9 +209,12 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
 /* Measurement reference: copy `bytes` (a multiple of 16) from device buffer
  * src to device buffer dst with 16-byte loads and stores on hip_stream, so
  * that the bandwidth a plain streaming kernel reaches on this device can be
- * put beside the step's.  streaming != 0 uses non-temporal stores (the store
- * policy of the step kernels on large lattices).  Enqueues only. */
-int mplb_copy_probe(const void* src, void* dst, size_t bytes, int streaming, void* hip_stream);
+ * put beside the step's.  kind 0: one element per thread and round, ordinary
+ * stores; 1: the same with non-temporal stores (the store policy of the step
+ * kernels on large lattices); 2: four elements per thread and round,
+ * non-temporal loads and stores, 16384 blocks of 256 threads.  Other kinds:
+ * MPLB_E_INVAL.  Enqueues only. */
+int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hip_stream);
 
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;
  * node n) of the current state with `value`, e.g. to plant a NaN. */

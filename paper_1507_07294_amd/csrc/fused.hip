@@ -356,9 +356,8 @@ struct PhiLoader {
   }
 
   // The pulls of logical plane zl (mapped onto the lattice), own node and
-  // halo, issued together so that the wave waits for memory once per plane;
-  // a thread without a halo position pulls a valid node (its column was set
-  // up from the tile corner) and drops the value.
+  // halo, issued together so that the wave waits for memory once per plane
+  // (lanes without a halo position are masked off for the halo pulls).
   struct Pending {
     F7Raw<P, PACK> own, halo[R::HPT];
   };
@@ -368,7 +367,8 @@ struct PhiLoader {
     int zo = mz * G.nx * G.ny;
     pull_f7_raw<P, PACK, XYWALL>(G, fin, own, p, zo, own_xy, pd.own);
 #pragma unroll
-    for (int k = 0; k < R::HPT; ++k) pull_f7_raw<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], pd.halo[k]);
+    for (int k = 0; k < R::HPT; ++k)
+      if (halo_on[k]) pull_f7_raw<P, PACK, XYWALL>(G, fin, halo[k], p, zo, halo_xy[k], pd.halo[k]);
   }
   // phi of the pulled plane into ring slot s; the own node's populations go
   // to q[i * NT + thread] when q is given
@@ -388,9 +388,11 @@ struct PhiLoader {
     }
 #pragma unroll
     for (int k = 0; k < R::HPT; ++k) {
-      T fh[7];
-      cvt_f7<P, PACK>(pd.halo[k], fh);
-      if (halo_on[k]) s[halo_lds[k]] = phi_of(fh);
+      if (halo_on[k]) {
+        T fh[7];
+        cvt_f7<P, PACK>(pd.halo[k], fh);
+        s[halo_lds[k]] = phi_of(fh);
+      }
     }
   }
   __device__ void load(const Geo& G, const void* fin, int zl, T* s, QT* q = nullptr) {

@@ -322,6 +322,22 @@ __global__ void __launch_bounds__(kBlock) k_copy16_nt(const u32x4* __restrict__ 
     __builtin_nontemporal_store(a[i], &b[i]);
 }
 
+// four elements per thread and round, non-temporal both ways; the rounds in
+// which every thread moves four, then one element per thread up to n
+__global__ void __launch_bounds__(kBlock) k_copy16_u4(const u32x4* __restrict__ a, u32x4* __restrict__ b, size_t n) {
+  const size_t T = (size_t)gridDim.x * kBlock, tid = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const size_t full = n / (4 * T);
+  for (size_t r = 0; r < full; ++r) {
+    const size_t base = r * 4 * T + tid;
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = __builtin_nontemporal_load(&a[base + u * T]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) __builtin_nontemporal_store(v[u], &b[base + u * T]);
+  }
+  for (size_t i = full * 4 * T + tid; i < n; i += T) __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
+}
+
 __global__ void k_fill_int(int* p, int v, int count) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = v;
@@ -455,8 +471,10 @@ hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, con
   MPLB_DISPATCH(P, return init_impl<PP>(mode, G, C, B, cur, s))
 }
 
-hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int streaming, hipStream_t s) {
-  if (streaming)
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int kind, hipStream_t s) {
+  if (kind == 2)
+    hipLaunchKernelGGL(k_copy16_u4, dim3(16384), dim3(kBlock), 0, s, (const u32x4*)src, (u32x4*)dst, bytes / 16);
+  else if (kind == 1)
     hipLaunchKernelGGL(k_copy16_nt, dim3(32768), dim3(kBlock), 0, s, (const u32x4*)src, (u32x4*)dst, bytes / 16);
   else
     hipLaunchKernelGGL(k_copy16, dim3(32768), dim3(kBlock), 0, s, (const float4*)src, (float4*)dst, bytes / 16);

@@ -51,7 +51,7 @@ hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, con
                        hipStream_t s);
 hipError_t launch_fill_int(int* p, int value, int count, hipStream_t s);
 // dst = src, 16-byte accesses (bandwidth reference); streaming: non-temporal stores
-hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int streaming, hipStream_t s);
+hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int kind, hipStream_t s);
 hipError_t launch_fill_zero(int P, void* p, int count, hipStream_t s);
 // overwrite stored population i (set 0: f, 1: g) at storage index n of buffer cur
 hipError_t launch_poke(int P, int mode, const Geo& G, const Bufs& B, int cur, int set, int i, int n, double v,

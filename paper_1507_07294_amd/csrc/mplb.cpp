@@ -642,10 +642,9 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
   return MPLB_OK;
 }
 
-int mplb_copy_probe(const void* src, void* dst, size_t bytes, int streaming, void* hip_stream) {
-  if (!src || !dst || bytes % 16) return MPLB_E_INVAL;
-  return launch_copy_probe(src, dst, bytes, streaming, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK
-                                                                                              : MPLB_E_DEVICE;
+int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hip_stream) {
+  if (!src || !dst || bytes % 16 || kind < 0 || kind > 2) return MPLB_E_INVAL;
+  return launch_copy_probe(src, dst, bytes, kind, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK : MPLB_E_DEVICE;
 }
 
 int mplb_poke(mplb_t* h, int set, int i, long node, double value) {

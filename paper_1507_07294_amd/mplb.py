@@ -294,13 +294,14 @@ def mplb_set_step_many_graphs(enable):
         raise MplbError(rc, "mplb_set_step_many_graphs")
 
 
-def mplb_copy_probe(src, dst, nbytes, streaming=False, stream=None):
-    """Device copy with 16-byte accesses (bandwidth reference); src, dst are torch tensors;
-    streaming: non-temporal stores."""
+def mplb_copy_probe(src, dst, nbytes, kind=0, stream=None):
+    """Device copy with 16-byte accesses (bandwidth reference); src, dst are torch tensors.
+    kind 0: one element per thread and round; 1: the same with non-temporal stores; 2: four
+    elements per thread and round, non-temporal loads and stores."""
     import torch
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     rc = lib().mplb_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), C.c_size_t(nbytes),
-                               C.c_int(1 if streaming else 0), C.c_void_p(int(s)))
+                               C.c_int(int(kind)), C.c_void_p(int(s)))
     if rc:
         raise MplbError(rc, "mplb_copy_probe")
 

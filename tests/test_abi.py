@@ -84,3 +84,11 @@ def test_binding_uses_a_single_hip_runtime():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_copy_probe_rejects_bad_arguments_before_any_device_call(lib):
+    fake = C.c_void_p(4096)
+    assert lib.mplb_copy_probe(fake, fake, C.c_size_t(64), 3, None) == mplb.MPLB_E_INVAL
+    assert lib.mplb_copy_probe(fake, fake, C.c_size_t(64), -1, None) == mplb.MPLB_E_INVAL
+    assert lib.mplb_copy_probe(fake, fake, C.c_size_t(60), 0, None) == mplb.MPLB_E_INVAL
+    assert lib.mplb_copy_probe(None, fake, C.c_size_t(64), 0, None) == mplb.MPLB_E_INVAL
