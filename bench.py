@@ -85,31 +85,42 @@ def time_lattice(lt, steps, warmup):
     return dt, [v / n_st for v in stages]
 
 
-def cpu_baseline(W, target_s=12.0):
-    """The FP64 oracle on a z-slab of the same Rayleigh-Taylor box."""
+def cpu_baseline(W, target_s=12.0, single_s=6.0):
+    """The FP64 oracle on z-slabs of the same Rayleigh-Taylor box: on every
+    host core (target_s of stepping), then on one thread (single_s, a thinner
+    slab)."""
     import oracle.orc as orc
     from paper_1507_07294_amd import workloads as wl
     w = wl.rayleigh_taylor(W=W, Re=4000.0)
-    nz_slab = max(8, W // 2)
-    z0 = w.shape[2] // 2 - nz_slab // 2
-    phi = w.phi0[z0:z0 + nz_slab].copy()
-    shape = (w.shape[0], w.shape[1], nz_slab)
-    o = orc.Oracle(shape, w.bc, orc.COUPLED, w.params)
-    o.init(phi)
-    # whole steps until target_s of CPU time has passed (at most 200 steps)
-    steps, elapsed = 0, 0.0
-    while elapsed < target_s and steps < 200:
-        t0 = time.perf_counter()
-        o.step(1)
-        elapsed += time.perf_counter() - t0
-        steps += 1
-    t1, t2 = elapsed, 0.0
-    nodes = shape[0] * shape[1] * shape[2]
-    mlups = nodes * steps / (t1 + t2) / 1e6
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+
+    def sample(nz_slab, budget_s):
+        z0 = w.shape[2] // 2 - nz_slab // 2
+        phi = w.phi0[z0:z0 + nz_slab].copy()
+        shape = (w.shape[0], w.shape[1], nz_slab)
+        o = orc.Oracle(shape, w.bc, orc.COUPLED, w.params)
+        o.init(phi)
+        # whole steps until budget_s of stepping has passed (at most 200 steps)
+        steps, elapsed = 0, 0.0
+        while elapsed < budget_s and steps < 200:
+            t0 = time.perf_counter()
+            o.step(1)
+            elapsed += time.perf_counter() - t0
+            steps += 1
+        nodes = shape[0] * shape[1] * shape[2]
+        return nodes * steps / elapsed / 1e6, steps, elapsed, f"{shape[0]}x{shape[1]}x{nz_slab}"
+
+    cores = orc.threads()
+    mlups, steps, secs, dims = sample(max(8, W // 2), target_s)
+    orc.set_threads(1)
+    try:
+        m1, s1, t1, d1 = sample(max(4, W // 32), single_s)
+    finally:
+        orc.set_threads(cores)
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
-            "sample": f"{shape[0]}x{shape[1]}x{nz_slab} z-slab through the interface of the W={W} "
-                      f"Rayleigh-Taylor box, {steps} FP64 steps, {t1 + t2:.1f} s"}
+            "sample": f"{dims} z-slab through the interface of the W={W} Rayleigh-Taylor box, "
+                      f"{steps} FP64 steps, {secs:.1f} s",
+            "single_thread": {"value": round(m1, 3), "unit": "MLUPS", "cores": 1,
+                              "sample": f"{d1} z-slab, {s1} FP64 steps, {t1:.1f} s"}}
 
 
 def main():

@@ -36,6 +36,7 @@
 #include "orc.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
@@ -924,3 +925,11 @@ int orc_set_state(orc_t* s, const double* f, const double* g, const double* phiu
   if (phiu) memcpy(s->phiu, phiu, 3 * s->N * sizeof(double));
   return ORC_OK;
 }
+
+int orc_set_threads(int n) {
+  if (n < 1) return -1;
+  omp_set_num_threads(n);
+  return 0;
+}
+
+int orc_get_threads(void) { return omp_get_max_threads(); }

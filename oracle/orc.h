@@ -116,6 +116,10 @@ void orc_mT(const double u[3], const double grad_rho[3], const double F[3], doub
 /* Isotropic finite differences (Eqs. 35, 36) of chi[N] on the lattice's
  * geometry: grad[3N], lap[N]. */
 int orc_grad_lap(const orc_t* s, const double* chi, double* grad, double* lap);
+/* Threads of the OpenMP loops (for timing the oracle on a given number of
+ * cores): set returns -1 for n < 1; get returns the current maximum. */
+int orc_set_threads(int n);
+int orc_get_threads(void);
 
 #ifdef __cplusplus
 }

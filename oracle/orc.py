@@ -82,8 +82,20 @@ def lib():
         L.orc_meq_g.argtypes = [C.c_double, C.c_double, dp, dp]
         L.orc_mT.argtypes = [dp, dp, dp, dp]
         L.orc_grad_lap.argtypes = [C.c_void_p, dp, dp, dp]
+        L.orc_set_threads.argtypes = [C.c_int]
+        L.orc_get_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def set_threads(n):
+    """Threads of the oracle's OpenMP loops (timing only)."""
+    if lib().orc_set_threads(int(n)) != 0:
+        raise ValueError(f"thread count {n}")
+
+
+def threads():
+    return int(lib().orc_get_threads())
 
 
 def _dp(a):

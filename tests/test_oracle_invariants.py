@@ -105,3 +105,25 @@ def test_nonfinite_is_reported_with_step_index():
     rc, msg = o.try_step(5)
     assert rc == orc.E_NONFINITE
     assert "after step 3" in msg
+
+
+def test_fields_do_not_depend_on_the_thread_count():
+    """Every node's update reads only the previous level, so one thread and
+    all threads give the same fields bit for bit (only the order of the
+    totals' reductions may differ)."""
+    w = wl.perturbed_case((12, 10, 9), (0, 0, 1), 41, coupled=True, sigma=0.02, D=2.0, ratio=3.0)
+    out = []
+    n0 = orc.threads()
+    try:
+        for t in (1, n0):
+            orc.set_threads(t)
+            o = orc.Oracle(w.shape, w.bc, orc.COUPLED, w.params)
+            o.init(w.phi0, w.u0)
+            o.step(5)
+            out.append([o.read(k) for k in ("phi", "mu", "ux", "uy", "uz", "p")])
+    finally:
+        orc.set_threads(n0)
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        orc.set_threads(0)
