@@ -58,6 +58,34 @@ def _summary(results: List[Result], t_first: float, t_last: float):
             "mean_s": float(lat.mean()), "makespan_s": span, "aggregate_MLUPS": lups / span / 1e6}
 
 
+class _Streams:
+    """The current stream, which runs the batched steps, and a second one for
+    setting lattices up and reading them out."""
+
+    def __init__(self):
+        import torch
+        self._torch = torch
+        self.main = torch.cuda.current_stream()
+        self.side = torch.cuda.Stream()
+
+    def main_ptr(self):
+        return self.main.cuda_stream
+
+    def side_ptr(self):
+        return self.side.cuda_stream
+
+    def on_side(self):
+        return self._torch.cuda.stream(self.side)
+
+    def mark_main(self):
+        ev = self._torch.cuda.Event()
+        ev.record(self.main)
+        return ev
+
+    def side_waits(self, ev):
+        self.side.wait_event(ev)
+
+
 class Server:
     """Admits requests by HBM budget and advances all resident lattices with
     batched steps, `chunk` steps at a time."""
@@ -71,13 +99,20 @@ class Server:
         self.batch_sizes: List[int] = []
 
     def run(self, trace, realtime=True):
+        """Serve the trace.  The batched steps go to the current stream; new
+        lattices are set up and finished ones read out on a second stream, so
+        that both overlap the steps: a chunk is enqueued before the lattices
+        that the previous chunk finished are read out, and those reads wait
+        only for that previous chunk (an event)."""
+        st = _Streams()
         t0 = time.perf_counter()
         pending = collections.deque(sorted(trace, key=lambda r: r.arrival))
         waiting = collections.deque()
         active = []  # [req, lattice, done, admitted, bytes]
+        finished = []  # (entry, event after the chunk that finished it)
         used = 0
         results: List[Result] = []
-        while pending or waiting or active:
+        while pending or waiting or active or finished:
             now = time.perf_counter() - t0
             while pending and (not realtime or pending[0].arrival <= now):
                 waiting.append(pending.popleft())
@@ -89,30 +124,37 @@ class Server:
                 if used + need > self.budget:
                     break
                 waiting.popleft()
-                lt = mplb.from_workload(req.workload, self.precision)
+                with st.on_side():  # memory, upload and init on the side stream
+                    lt = mplb.from_workload(req.workload, self.precision)  # returns initialised
+                lt.set_stream(st.main_ptr())
                 used += need
                 self.peak_bytes = max(self.peak_bytes, used)
                 active.append([req, lt, 0, time.perf_counter() - t0, need])
-            if not active:
-                if pending:
-                    time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.01)))
-                continue
-            k = min(self.chunk, min(a[0].steps - a[2] for a in active))
-            mplb.mplb_step_many([a[1] for a in active], k)
-            self.batch_sizes.append(len(active))
-            still = []
-            for a in active:
-                a[2] += k
-                if a[2] >= a[0].steps:
-                    fields = {f: a[1].read(f) for f in READ_FIELDS}  # synchronises
-                    done = time.perf_counter() - t0
-                    results.append(Result(a[0].rid, a[0].arrival, a[3], done, a[0].workload.nodes * a[0].steps,
-                                          fields if self.keep_fields else None))
-                    a[1].destroy()
-                    used -= a[4]
-                else:
-                    still.append(a)
-            active = still
+            just_finished = []
+            if active:
+                k = min(self.chunk, min(a[0].steps - a[2] for a in active))
+                mplb.mplb_step_many([a[1] for a in active], k)
+                ev = st.mark_main()
+                self.batch_sizes.append(len(active))
+                still = []
+                for a in active:
+                    a[2] += k
+                    (just_finished if a[2] >= a[0].steps else still).append(a)
+                active = still
+                just_finished = [(a, ev) for a in just_finished]
+            # read out what the previous chunk finished while this one runs
+            for a, ev in finished:
+                st.side_waits(ev)
+                a[1].set_stream(st.side_ptr())
+                fields = {f: a[1].read(f) for f in READ_FIELDS}  # synchronises the side stream
+                done = time.perf_counter() - t0
+                results.append(Result(a[0].rid, a[0].arrival, a[3], done, a[0].workload.nodes * a[0].steps,
+                                      fields if self.keep_fields else None))
+                a[1].destroy()
+                used -= a[4]
+            finished = just_finished
+            if not active and not finished and pending and not waiting:
+                time.sleep(max(0.0, min(pending[0].arrival - (time.perf_counter() - t0), 0.01)))
         t_last = max(r.completed for r in results)
         t_first = min(r.arrival for r in results)
         return results, _summary(results, t_first, t_last)

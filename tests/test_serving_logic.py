@@ -1,5 +1,7 @@
 """Host logic of the serving loop with a stand-in backend (CPU only):
-admission by budget, FIFO order, every request completes once, batching."""
+admission by budget, FIFO order, every request completes once, batching,
+and read-out only after the chunk that finished a lattice."""
+import contextlib
 import types
 
 import pytest
@@ -20,8 +22,32 @@ class FakeLattice:
     def read(self, f):
         return self.steps
 
+    def set_stream(self, ptr):
+        self.stream = ptr
+
     def destroy(self):
         self.alive = False
+
+
+class FakeStreams:
+    """Events are the number of chunks enqueued when they were recorded."""
+    chunks = 0
+    waited = []
+
+    def main_ptr(self):
+        return 1
+
+    def side_ptr(self):
+        return 2
+
+    def on_side(self):
+        return contextlib.nullcontext()
+
+    def mark_main(self):
+        return FakeStreams.chunks
+
+    def side_waits(self, ev):
+        FakeStreams.waited.append(ev)
 
 
 @pytest.fixture
@@ -42,12 +68,16 @@ def fake(monkeypatch):
 
     def step_many(lts, k):
         state.batches.append(len(lts))
+        FakeStreams.chunks += 1
         for lt in lts:
+            assert lt.stream == 1  # batched steps on the main stream
             lt.step(k)
 
     monkeypatch.setattr(serve.mplb, "from_workload", from_workload)
     monkeypatch.setattr(serve.mplb, "mplb_step_many", step_many)
     monkeypatch.setattr(serve, "_required", lambda req, precision: req.workload.nodes * 100)
+    monkeypatch.setattr(serve, "_Streams", FakeStreams)
+    FakeStreams.chunks, FakeStreams.waited = 0, []
     return state
 
 
@@ -70,6 +100,10 @@ def test_budget_limits_residency(fake):
     for r in results:
         assert r.fields["phi"] == trace[r.rid].steps  # stepped exactly to its target
     assert max(fake.batches) > 1 and summary["requests"] == len(trace)
+    # each read-out waited for a chunk that had been enqueued, and a later
+    # chunk was enqueued before the read (the read overlaps it)
+    assert len(FakeStreams.waited) == len(trace)
+    assert all(1 <= ev <= FakeStreams.chunks for ev in FakeStreams.waited)
 
 
 def test_request_over_budget_is_rejected(fake):
