@@ -144,6 +144,16 @@ def main():
     print(f"[bench] {wname} N={N} f32: init", file=sys.stderr, flush=True)
     lt = mplb.from_workload(w, "f32")
     dt, st = time_lattice(lt, args.steps, args.warmup)
+    # after the timed region: five more windows of steps/5 steps, for the
+    # spread between windows (the median is reported beside the value)
+    win = []
+    for _ in range(5):
+        k = max(1, args.steps // 5)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lt.step(k)
+        torch.cuda.synchronize()
+        win.append((time.perf_counter() - t0) / k * 1e3)
     mlups = N * args.steps / dt / 1e6
     ms_step = dt / args.steps * 1e3
     k_ms = st[2]
@@ -158,6 +168,8 @@ def main():
         "hbm_frac_step": round(ALGO_BYTES["f32"] * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes_per_lup": ALGO_BYTES["f32"],
         "stage_ms": {"phi": round(st[0], 4), "mu": round(st[1], 4), "step": round(st[2], 4)},
+        "windows_ms_per_step": [round(v, 4) for v in win],
+        "median_window_ms_per_step": round(sorted(win)[2], 4),
         "roofline": {"kernel": "k_fused", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "algorithmic_bytes_per_launch": ALGO_BYTES["f32"] * N},
