@@ -21,13 +21,16 @@ def _trace():
     return reqs
 
 
-def test_mix_equals_alone_and_budget_holds():
+@pytest.mark.parametrize("precision", ["f32", "f16", "bf16"])
+def test_mix_equals_alone_and_budget_holds(precision):
     from paper_1507_07294_amd import mplb
     from paper_1507_07294_amd.serve import Server
+    print(f"\n[case] serving mix {precision}", flush=True)
     trace = _trace()
-    sizes = [mplb.mplb_required_bytes(*r.workload.shape, mplb.MPLB_F32, mplb.MPLB_COUPLED) for r in trace]
+    sizes = [mplb.mplb_required_bytes(*r.workload.shape, mplb.PRECISIONS[precision], mplb.MPLB_COUPLED)
+             for r in trace]
     budget = sorted(sizes)[-1] + sorted(sizes)[-2] + 1  # about two lattices at a time: admission waits
-    srv = Server("f32", budget, chunk=40, keep_fields=True)
+    srv = Server(precision, budget, chunk=40, keep_fields=True)
     results, summary = srv.run(trace, realtime=False)
     print(f"\n[serving] {summary} peak={srv.peak_bytes} budget={budget} batches={srv.batch_sizes}", flush=True)
     assert srv.peak_bytes <= budget
@@ -35,26 +38,28 @@ def test_mix_equals_alone_and_budget_holds():
     assert len(results) == len(trace)
     for res in results:
         req = trace[res.rid]
-        lt = mplb.from_workload(req.workload, "f32")
+        lt = mplb.from_workload(req.workload, precision)
         lt.step(req.steps)
         for f, v in res.fields.items():
             assert np.array_equal(v, lt.read(f)), (res.rid, f)
         lt.destroy()
 
 
-def test_step_many_mixed_walls_and_parity():
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_step_many_mixed_walls_and_parity(precision):
     """Lattices at different step parities and with walls on x or y batch
     together correctly."""
     from paper_1507_07294_amd import mplb
+    print(f"\n[case] step_many walls and parity {precision}", flush=True)
     ws = [wl.perturbed_case((20, 18, 16), (0, 0, 1), 91), wl.perturbed_case((17, 21, 15), (1, 0, 0), 92),
           wl.perturbed_case((33, 9, 12), (0, 1, 1), 93)]
     alone = []
     for i, w in enumerate(ws):
-        g = mplb.from_workload(w, "f32")
+        g = mplb.from_workload(w, precision)
         g.step(13 + i)
         alone.append({k: g.read(k) for k in ("phi", "ux", "p")})
         g.destroy()
-    mix = [mplb.from_workload(w, "f32") for w in ws]
+    mix = [mplb.from_workload(w, precision) for w in ws]
     mix[1].step(1)
     mix[2].step(2)
     mplb.mplb_step_many(mix, 13)
