@@ -319,7 +319,7 @@ def _full_size_case(W=256):
     return w
 
 
-@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3)])
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_full_size_sampled(precision, tol):
     """256 x 256 x 1024 in the launch configuration the benchmark times: the
     GPU fields after 2 steps equal the FP64 oracle, evaluated on a window around
