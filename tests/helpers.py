@@ -103,7 +103,7 @@ def window_oracle_fields(w, node_xyz, steps):
     # axes wrap (onto themselves when the window is narrower than the axis)
     bc = tuple(w.bc)
     sw = wl.Workload(w.name + "_window", (len(ix), len(iy), len(iz)), bc, w.coupled, w.params, phi, u0=u0,
-                     velocity=w.velocity)
+                     velocity=w.velocity, nse_q=w.nse_q)
     o = oracle_for(sw)
     o.step(steps)
     return {k: float(o.read(k)[cz, cy, cx]) for k in (FIELDS if w.coupled else ("phi", "mu"))}

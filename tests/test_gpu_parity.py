@@ -9,6 +9,7 @@ helpers.FLOORS (1e-6 for phi, rho, u; 1e-5 for p; 1e-8 for mu; lattice units):
 On the two whole boxes at the workloads' full sizes (_full_field_check), mu is
 held to the bound its phi error implies and u is compared as a vector.
 The measured errors are printed for every case."""
+import dataclasses
 import functools
 
 import numpy as np
@@ -326,9 +327,17 @@ def test_full_size_sampled(precision, tol):
     each sampled node, at tile edges (x = 63/64, y = 7/8), z-segment edges and
     both walls.  Error per field: max |gpu - oracle| over the samples divided by
     the field's largest magnitude there."""
-    w = _full_size_case()
+    _sampled_check(_full_size_case(), precision, tol)
+
+
+def test_full_size_sampled_d3q19():
+    """The same check for the D3Q19 variant of the NSE lattice (FP32)."""
+    _sampled_check(dataclasses.replace(_full_size_case(), nse_q=19), "f32", F32_TOL)
+
+
+def _sampled_check(w, precision, tol):
     nx, ny, nz = w.shape
-    print(f"\n[case] full-size {w.shape} {precision}", flush=True)
+    print(f"\n[case] full-size {w.shape} D3Q{w.nse_q} {precision}", flush=True)
     g = helpers.gpu_for(w, precision)
     steps = 2
     g.step(steps)
