@@ -261,6 +261,10 @@ def main():
         finally:
             mplb.mplb_set_step_many_graphs(True)
         _, b2b = serve.run_back_to_back(trace, "f32", chunk=50)
+        # the same trace with FP16 population storage (its field error against
+        # the FP64 oracle is stated by the parity tests: 5e-3 relative L2)
+        srv16 = serve.Server("f16", 16e9, chunk=50)
+        _, mix16 = srv16.run(trace)
         result["serving"] = {
             "trace": f"{args.serving_requests} requests, Poisson arrivals (mean gap 3 ms, seed 20261202), half "
                      f"droplets (32^3..128^3) half Rayleigh-Taylor (W = 32..64), {args.serving_steps} steps each, "
@@ -268,6 +272,7 @@ def main():
             "batched": {k: round(v, 4) for k, v in mix.items()},
             "batched_without_graphs": {k: round(v, 4) for k, v in mix_nog.items()},
             "back_to_back": {k: round(v, 4) for k, v in b2b.items()},
+            "batched_f16_storage": {k: round(v, 4) for k, v in mix16.items()},
             "mean_batch": round(float(sum(srv.batch_sizes) / max(1, len(srv.batch_sizes))), 2),
             "peak_bytes": srv.peak_bytes}
 
