@@ -403,6 +403,12 @@ struct ChunkGraph {
   unsigned long long used = 0;
 };
 constexpr int kGraphCache = 4;
+// An evicted graph is never one that may still be executing: before a chunk
+// is built or looked up, mplb_step_many waits on the host for the previous
+// chunk's table upload, which follows every earlier chunk in stream order.
+// So only the most recently used graph can still run, and the
+// least-recently-used eviction never picks it.
+static_assert(kGraphCache >= 2, "the running chunk's graph must survive one eviction");
 
 // Device table of a batched step and its pinned host staging (grow-only,
 // one per device; batched calls on one device are not thread-safe).
