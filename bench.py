@@ -26,7 +26,7 @@ HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E
 # algorithmic bytes per lattice update (22 populations + 3-word (phi u)
 # history, each read and written once), per storage mode
 ALGO_BYTES = {"f64": 400, "f32": 200, "f16": 116, "bf16": 116}
-Q19_ALGO_BYTES = {"f64": 464, "f32": 232}  # D3Q19: 19 g instead of 15
+Q19_ALGO_BYTES = {"f64": 464, "f32": 232, "f16": 132, "bf16": 132}  # D3Q19: 19 g instead of 15
 CHE_ALGO_BYTES = {"f64": 2 * 8 * 8, "f32": 2 * 4 * 8}  # 7 populations + phi of the previous level
 
 
@@ -196,19 +196,21 @@ def main():
         result["variants"] = variants
 
     if not args.no_q19:
-        print(f"[bench] {wname} f32 D3Q19", file=sys.stderr, flush=True)
-        w.nse_q = 19
-        lt = mplb.from_workload(w, "f32")
-        w.nse_q = 15
-        steps = max(10, args.steps // 2)
-        dtq, stq = time_lattice(lt, steps, max(2, args.warmup // 2))
-        result["d3q19"] = {"MLUPS": round(N * steps / dtq / 1e6, 1), "ms_per_step": round(dtq / steps * 1e3, 4),
-                           "algorithmic_bytes_per_lup": Q19_ALGO_BYTES["f32"],
-                           "hbm_frac_step": round(Q19_ALGO_BYTES["f32"] * N / (dtq / steps) / 1e9 / HBM_PEAK_GBPS, 4),
-                           "k_step_ms": round(stq[2], 4)}
-        lt.destroy()
-        del lt
-        torch.cuda.empty_cache()
+        for prec in ("f32", "f16"):
+            print(f"[bench] {wname} {prec} D3Q19", file=sys.stderr, flush=True)
+            w.nse_q = 19
+            lt = mplb.from_workload(w, prec)
+            w.nse_q = 15
+            steps = max(10, args.steps // 2)
+            dtq, stq = time_lattice(lt, steps, max(2, args.warmup // 2))
+            rec = {"MLUPS": round(N * steps / dtq / 1e6, 1), "ms_per_step": round(dtq / steps * 1e3, 4),
+                   "algorithmic_bytes_per_lup": Q19_ALGO_BYTES[prec],
+                   "hbm_frac_step": round(Q19_ALGO_BYTES[prec] * N / (dtq / steps) / 1e9 / HBM_PEAK_GBPS, 4),
+                   "k_step_ms": round(stq[2], 4)}
+            result["d3q19" if prec == "f32" else f"d3q19_{prec}"] = rec
+            lt.destroy()
+            del lt
+            torch.cuda.empty_cache()
 
     if not args.no_che:
         wc = wl.deformation_flow(n=128)

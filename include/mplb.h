@@ -61,7 +61,8 @@ extern "C" {
  * (0,-1,-1), (0,1,-1), (0,-1,1)); weights 1/3, 1/18, 1/36.  The collision
  * relaxes the five stress moments of d'Humieres' D3Q19 basis at 1/tau_g
  * (Eq. 33) and every other moment at 1 (lambda_g is not used); g^eq and the
- * source are Eqs. 21 and 28 taken exactly.  FP64 and FP32 storage only;
+ * source are Eqs. 21 and 28 taken exactly.  Every storage precision; with
+ * 16-bit storage f_i and g_i (i = 1..6) share 32-bit words as on D3Q15.
  * mplb_step_many steps such lattices one after another. */
 #define MPLB_COUPLED_Q19 2
 
@@ -112,8 +113,8 @@ typedef struct mplb_s mplb_t;
 
 /* Device bytes a lattice needs (populations of two time levels, the
  * (phi u) history (3 words per node; CHE-only: phi, 1 word), phi, mu, a
- * read-out buffer and reduction scratch).  MPLB_E_INVAL for a mode and
- * precision that do not go together (MPLB_COUPLED_Q19 with 16-bit storage). */
+ * read-out buffer and reduction scratch).  MPLB_E_INVAL for an unknown mode
+ * or precision, or dimensions out of range. */
 int mplb_required_bytes(int nx, int ny, int nz, int precision, int mode, size_t* bytes);
 
 /* Create a lattice of nx*ny*nz nodes (each >= 1) with bc[a] in

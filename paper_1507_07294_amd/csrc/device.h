@@ -40,11 +40,12 @@ __host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i 
 // ---------------------------------------------------------------- storage
 // Population storage of one time level, in a buffer for f and one for g.
 //   f buffer: f_0 (S0, `pitch` elements), then f_1..f_6;
-//   g buffer: g_0..g_14 (S), each array `pitch` elements.
+//   g buffer: g_0..g_{Q-1} (S), each array `pitch` elements.
 // PACK (16-bit populations of the coupled model): f_i and g_i, i = 1..6,
 // share a velocity and therefore a pull source, so they are stored together
 // in one 32-bit word (f_i in the low half, g_i in the high half) in six
-// arrays after f_0; the g buffer then holds g_0 and the corners g_7..g_14.
+// arrays after f_0; the g buffer then holds g_0 and g_7..g_{Q-1} (the
+// corners of D3Q15, the edges of D3Q19).
 template <int P, bool PACK>
 struct Lat {
   using T = typename Prec<P>::T;

@@ -463,7 +463,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   using T = typename Prec<P>::T;
   using R = Ring<P, TY, 2>;
   using MU = MuMaker<P, TY>;
-  constexpr bool PACK = packed<P, true>() && Q == 15;
+  constexpr bool PACK = packed<P, true>();
   using L = Lat<P, PACK>;
   using LD = PhiLoader<P, TY, 2, XYWALL, PACK>;
   using QT = typename LD::QT;
@@ -608,7 +608,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
       for (int i = 1; i < 7; ++i) st_at<NT>(wa + ((size_t)(i - 1) * G.pitch + zo), col_xy, L::pack(f[i], g[i]));
       st_at<NT>(ga + zo, col_xy, (S)g[0]);
 #pragma unroll
-      for (int i = 7; i < 15; ++i) st_at<NT>(ga + (L::gslot(i) * G.pitch + zo), col_xy, (S)g[i]);
+      for (int i = 7; i < Q; ++i) st_at<NT>(ga + (L::gslot(i) * G.pitch + zo), col_xy, (S)g[i]);
     } else {
       S* fa = L::fi(fo, G.pitch);
 #pragma unroll
@@ -775,11 +775,9 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     if (mode == MPLB_COUPLED)
       hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15, V>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
-    else if constexpr (P == MPLB_F64 || P == MPLB_F32)  // D3Q19: FP64 and FP32 storage; its forcing is Gamma T
+    else  // D3Q19: its forcing is Gamma T, so only the stencil switch applies
       hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B,
                          cur, tl);
-    else
-      return hipErrorInvalidValue;
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
@@ -942,7 +940,7 @@ size_t fused_stream_threshold() { return kStreamBytes; }
 size_t fused_step_bytes(int P, int mode, long long N) {
   // populations and history read and written once per update
   size_t per = mode == MPLB_COUPLED       ? (P == MPLB_F64 ? 400 : (P == MPLB_F32 ? 200 : 116))
-               : mode == MPLB_COUPLED_Q19 ? (P == MPLB_F64 ? 464 : 232)
+               : mode == MPLB_COUPLED_Q19 ? (P == MPLB_F64 ? 464 : (P == MPLB_F32 ? 232 : 132))
                                           : (P == MPLB_F64 ? 128 : 64);
   return per * (size_t)N;
 }

@@ -29,10 +29,10 @@ using namespace dev;
 // ------------------------------------------------------------------ kernels
 constexpr int kBlock = 256;
 
-// Q: velocities of the NSE lattice (15 or 19); the 16-bit packing of f_i
-// with g_i exists for D3Q15 only.
+// Q: velocities of the NSE lattice (15 or 19); 16-bit populations of either
+// lattice pack f_i with g_i (i = 1..6, the same face velocities).
 template <int P, bool COUPLED, int Q>
-constexpr bool packed_q() { return packed<P, COUPLED>() && Q == 15; }
+constexpr bool packed_q() { return packed<P, COUPLED>(); }
 
 template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_phi(Geo G, Bufs B, int cur) {

@@ -38,11 +38,12 @@ Plan make_plan(long long N, int prec, int mode) {
   const size_t A = 256;
   size_t sT = comp_size(prec), s0 = store0_size(prec), sS = store_size(prec);
   // 16-bit populations of the coupled model: f_i and g_i (i = 1..6) share
-  // 32-bit words in the f buffer; the g buffer keeps g_0 and the 8 corners
-  bool pack = mode == MPLB_COUPLED && sS == 2;
+  // 32-bit words in the f buffer; the g buffer keeps g_0 and g_7..g_{q-1}
+  // (the 8 corners of D3Q15, the 12 edges of D3Q19)
+  bool pack = mode != MPLB_CHE_ONLY && sS == 2;
   const int q = mode == MPLB_COUPLED_Q19 ? 19 : 15;  // NSE lattice
   p.f = align_up(p.pitch * s0 + 6 * p.pitch * (pack ? 4 : sS), A);
-  p.g = mode != MPLB_CHE_ONLY ? align_up((pack ? 9 : q) * p.pitch * sS, A) : 0;
+  p.g = mode != MPLB_CHE_ONLY ? align_up((pack ? q - 6 : q) * p.pitch * sS, A) : 0;
   // (phi u) history: 3 words (coupled); phi alone where u is prescribed
   p.phiu = align_up((mode != MPLB_CHE_ONLY ? 3 : 1) * p.pitch * sT, A);
   p.phi = align_up(p.pitch * sT, A);
@@ -60,8 +61,7 @@ Plan make_plan(long long N, int prec, int mode) {
 // modes and the precisions each supports
 bool valid_mode(int mode, int precision) {
   if (precision < MPLB_F64 || precision > MPLB_F32_BF16) return false;
-  if (mode == MPLB_COUPLED || mode == MPLB_CHE_ONLY) return true;
-  return mode == MPLB_COUPLED_Q19 && (precision == MPLB_F64 || precision == MPLB_F32);
+  return mode == MPLB_COUPLED || mode == MPLB_CHE_ONLY || mode == MPLB_COUPLED_Q19;
 }
 
 bool valid_dims(int nx, int ny, int nz) {

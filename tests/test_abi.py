@@ -40,13 +40,19 @@ def test_host_only_calls(lib):
     assert lib.mplb_required_bytes(0, 32, 32, mplb.MPLB_F64, mplb.MPLB_COUPLED, C.byref(n)) == mplb.MPLB_E_INVAL
     assert lib.mplb_required_bytes(32, 32, 32, 7, mplb.MPLB_COUPLED, C.byref(n)) == mplb.MPLB_E_INVAL
     assert lib.mplb_required_bytes(1 << 11, 1 << 11, 1 << 11, 0, 0, C.byref(n)) == mplb.MPLB_E_INVAL
-    # D3Q19: four more population arrays per level than D3Q15; FP64/FP32 only
+    # D3Q19: four more population arrays per level than D3Q15, in every
+    # storage precision (16 bit: four more 2-byte arrays)
     q, r = C.c_size_t(0), C.c_size_t(0)
     assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F64, mplb.MPLB_COUPLED, C.byref(r)) == 0
     assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F64, mplb.MPLB_COUPLED_Q19, C.byref(q)) == 0
     assert q.value >= r.value + 2 * 4 * 32 ** 3 * 8
-    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F32_F16, mplb.MPLB_COUPLED_Q19, C.byref(q)) == mplb.MPLB_E_INVAL
-    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F32_BF16, mplb.MPLB_COUPLED_Q19, C.byref(q)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F32, mplb.MPLB_COUPLED, C.byref(r)) == 0
+    assert lib.mplb_required_bytes(32, 32, 32, mplb.MPLB_F32, mplb.MPLB_COUPLED_Q19, C.byref(q)) == 0
+    extra32 = q.value - r.value
+    for prec in (mplb.MPLB_F32_F16, mplb.MPLB_F32_BF16):
+        assert lib.mplb_required_bytes(32, 32, 32, prec, mplb.MPLB_COUPLED, C.byref(r)) == 0
+        assert lib.mplb_required_bytes(32, 32, 32, prec, mplb.MPLB_COUPLED_Q19, C.byref(q)) == 0
+        assert abs((q.value - r.value) - extra32 / 2) <= 2 * 256  # the same four arrays at 2 bytes
 
 
 def test_invalid_create_is_rejected_before_any_device_call(lib):

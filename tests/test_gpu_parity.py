@@ -92,6 +92,31 @@ def test_coupled_q19_f32():
     _compare(w, [1, 10, 100], "f32", F32_TOL)
 
 
+@pytest.mark.parametrize("precision", ["f16", "bf16"])
+@pytest.mark.parametrize("shape,bc,seed", [((24, 20, 18), (0, 0, 1), 46), ((9, 10, 11), (1, 1, 1), 47)])
+def test_coupled_q19_16bit(precision, shape, bc, seed):
+    """D3Q19 with 16-bit population storage (f_i and g_i packed as on
+    D3Q15) against the FP64 oracle, 200 steps, 5e-3 (FP16) and 5e-2 (BF16)
+    on every field; a checkpoint restores bitwise and step_many equals
+    separate steps."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case(shape, bc, seed, coupled=True, ratio=4.0)
+    w.nse_q = 19
+    _, g = _compare(w, [1, 10, 100, 200], precision, 5e-3 if precision == "f16" else 5e-2)
+    blob = g.checkpoint()
+    g.step(4)
+    after = {k: g.read(k) for k in ("phi", "ux", "p")}
+    g.restore(blob)
+    g.step(4)
+    for k, v in after.items():
+        assert np.array_equal(g.read(k), v), k
+    a, b = helpers.gpu_for(w, precision), helpers.gpu_for(w, precision)
+    mplb.mplb_step_many([a], 6)
+    b.step(6)
+    for k in ("phi", "uz", "p"):
+        assert np.array_equal(a.read(k), b.read(k)), k
+
+
 def test_q19_totals_checkpoint_and_batch():
     """D3Q19: FP64 totals equal the oracle's, the GPU momentum balance holds,
     a checkpoint restores bitwise, and step_many (one lattice after another
@@ -330,9 +355,10 @@ def test_full_size_sampled(precision, tol):
     _sampled_check(_full_size_case(), precision, tol)
 
 
-def test_full_size_sampled_d3q19():
-    """The same check for the D3Q19 variant of the NSE lattice (FP32)."""
-    _sampled_check(dataclasses.replace(_full_size_case(), nse_q=19), "f32", F32_TOL)
+@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3)])
+def test_full_size_sampled_d3q19(precision, tol):
+    """The same check for the D3Q19 variant of the NSE lattice."""
+    _sampled_check(dataclasses.replace(_full_size_case(), nse_q=19), precision, tol)
 
 
 def _sampled_check(w, precision, tol):
