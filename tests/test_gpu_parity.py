@@ -178,7 +178,7 @@ def test_switches_che_only_and_16bit():
 
 
 @pytest.mark.parametrize("kind", ["field", "zalesak", "deformation"])
-@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2)])
 def test_che_only(kind, precision, tol):
     shape, bc = (30, 26, 22), (0, 0, 0)
     w = wl.perturbed_case(shape, bc, 21, coupled=False)
