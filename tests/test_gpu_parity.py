@@ -321,12 +321,17 @@ def test_step_many_equals_single_runs():
 
 
 @pytest.mark.parametrize("precision", ["f16", "bf16"])
-def test_storage_precision_error(precision):
+@pytest.mark.parametrize("shape,bc,seed", [
+    ((24, 20, 18), (0, 0, 1), 81),  # walls in z
+    ((9, 10, 11), (1, 1, 1), 82),   # walls on every axis (the x/y-wall instantiation)
+    ((70, 37, 29), (0, 1, 0), 83),  # several tiles, a ragged tail, walls in y only
+])
+def test_storage_precision_error(precision, shape, bc, seed):
     """16-bit population storage (f_0 and the history stay FP32): the error
-    against the FP64 oracle after 200 steps of a perturbed droplet between
-    walls is reported; the bound is 5e-3 (FP16) and 5e-2 (BF16) relative L2
-    on every field."""
-    w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 81, coupled=True)
+    against the FP64 oracle after 200 steps of a perturbed droplet is
+    reported; the bound is 5e-3 (FP16) and 5e-2 (BF16) relative L2 on every
+    field."""
+    w = wl.perturbed_case(shape, bc, seed, coupled=True)
     tol = 5e-3 if precision == "f16" else 5e-2
     _compare(w, [1, 10, 100, 200], precision, tol)
 
