@@ -66,8 +66,17 @@ def test_coupled_f64(shape, bc, seed):
     _compare(w, [1, 10, 60], "f64", F64_TOL)
 
 
-@pytest.mark.parametrize("shape,bc,seed", [((24, 20, 18), (0, 0, 1), 11), ((70, 37, 29), (0, 0, 1), 12)])
+@pytest.mark.parametrize("shape,bc,seed", [
+    ((24, 20, 18), (0, 0, 1), 11),
+    ((70, 37, 29), (0, 0, 1), 12),
+    ((9, 10, 11), (1, 1, 1), 13),   # walls on every axis (the x/y-wall instantiation)
+    ((33, 5, 40), (0, 0, 0), 14),   # fully periodic, thin in y
+])
 def test_coupled_f32(shape, bc, seed):
+    """FP32 against the oracle on the geometries of the FP64 test, less the
+    degenerate boxes (one column, one layer, one node): there a velocity
+    component is near zero and its relative error is round-off alone; FP64
+    covers them at 1e-12 through the same code."""
     w = wl.perturbed_case(shape, bc, seed, coupled=True)
     _compare(w, [1, 10, 100], "f32", F32_TOL)
 
