@@ -167,7 +167,7 @@ def main():
                    "boundaries": "periodic x,y; bounce-back walls z", "Re": 4000, "atwood": 0.5},
         "hbm_frac_step": round(ALGO_BYTES["f32"] * N / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "algorithmic_bytes_per_lup": ALGO_BYTES["f32"],
-        "stage_ms": {"phi": round(st[0], 4), "mu": round(st[1], 4), "step": round(st[2], 4)},
+        "stage_ms": {"step": round(st[2], 4)},
         "windows_ms_per_step": [round(v, 4) for v in win],
         "median_window_ms_per_step": round(sorted(win)[2], 4),
         "roofline": {"kernel": "k_fused", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS,

@@ -186,7 +186,8 @@ int mplb_front(mplb_t* h, double out[2]);
  * its shape.  Each lattice computes exactly what mplb_step computes for it.
  * All handles must be initialised, share one precision and mode, and use the
  * first handle's stream.  Not thread-safe across calls on one device.
- * CHE-only lattices are stepped one after another. */
+ * CHE-only and D3Q19 lattices, and lattices with a study switch set, are
+ * stepped one after another (the batched kernel is the default D3Q15 step). */
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
 
 /* Whether mplb_step_many replays its steps as a graph (enable != 0, the
@@ -201,9 +202,9 @@ int mplb_checkpoint(mplb_t* h, void* host_buf, size_t bytes);
 int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes);
 
 /* Measurement: advance nsteps steps with HIP events recorded on the handle's
- * stream around each kernel stage; ms[0..3] receive the summed durations of
- * a separate phi pass, a separate mu pass (both 0 when, as now, one kernel
- * does the whole step), the collide-and-stream kernel and the whole steps.
+ * stream around each step kernel; ms[2] and ms[3] receive the summed
+ * duration of the step kernels (one kernel does the whole step), ms[0] and
+ * ms[1] (separate phi and mu passes, which the step does not have) are 0.
  * Synchronises; the state advances exactly as with mplb_step. */
 int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
 

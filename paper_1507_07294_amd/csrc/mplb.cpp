@@ -363,17 +363,23 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
   if (!h || !ms || nsteps < 0) return MPLB_E_INVAL;
   if (!h->have_init) return fail(h, MPLB_E_STATE, "step before init");
   for (int k = 0; k < 4; ++k) ms[k] = 0.0;
-  std::vector<hipEvent_t> ev(4 * (size_t)nsteps);
-  for (auto& e : ev) HIPCHK(h, hipEventCreate(&e));
+  // one kernel does the whole step: events around it, none for the separate
+  // phi and mu passes that the step no longer has (their entries stay 0)
+  std::vector<hipEvent_t> ev;
+  ev.reserve(2 * (size_t)nsteps);
   int rc = MPLB_OK;
+  for (size_t k = 0; k < 2 * (size_t)nsteps && rc == MPLB_OK; ++k) {
+    hipEvent_t e = nullptr;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
+    else ev.push_back(e);
+  }
   for (int k = 0; k < nsteps && rc == MPLB_OK; ++k) {
-    hipEvent_t* e = &ev[4 * (size_t)k];
+    hipEvent_t* e = &ev[2 * (size_t)k];
     set_vel_time(h);
     hipError_t err = hipEventRecord(e[0], h->stream);
-    if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
-    if (err == hipSuccess) err = hipEventRecord(e[2], h->stream);
     if (err == hipSuccess) err = launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream);
-    if (err == hipSuccess) err = hipEventRecord(e[3], h->stream);
+    if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
     if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
     h->cur = 1 - h->cur;
     h->step++;
@@ -383,13 +389,11 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
     if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
   }
   for (int k = 0; k < nsteps && rc == MPLB_OK; ++k) {
-    hipEvent_t* e = &ev[4 * (size_t)k];
-    float a = 0, b = 0, c = 0;
-    (void)hipEventElapsedTime(&a, e[0], e[1]);
-    (void)hipEventElapsedTime(&b, e[1], e[2]);
-    (void)hipEventElapsedTime(&c, e[2], e[3]);
-    ms[0] += a; ms[1] += b; ms[2] += c; ms[3] += a + b + c;
+    float c = 0;
+    (void)hipEventElapsedTime(&c, ev[2 * (size_t)k], ev[2 * (size_t)k + 1]);
+    ms[2] += c;
   }
+  ms[3] = ms[2];
   for (auto& e : ev) (void)hipEventDestroy(e);
   return rc;
 }

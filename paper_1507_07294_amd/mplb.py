@@ -258,7 +258,8 @@ class Lattice:
         self._chk(lib().mplb_restore(self._h, buf.ctypes.data_as(C.c_void_p), C.c_size_t(buf.size)))
 
     def time_stages(self, n):
-        """Summed event-timed milliseconds of (phi pass, mu pass, step kernel, whole step) over n steps."""
+        """Advance n steps and return the summed event-timed milliseconds of (phi pass, mu pass,
+        step kernel, whole step); one kernel does the whole step, so the first two are 0."""
         out = np.zeros(4, dtype=np.float64)
         self._chk(lib().mplb_time_stages(self._h, int(n), _dp(out)))
         return out
