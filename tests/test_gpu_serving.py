@@ -133,3 +133,31 @@ def test_step_many_with_untruncated_forcing():
         for k, v in ref.items():
             assert np.array_equal(g.read(k), v), k
         g.destroy()
+
+
+def test_nan_in_one_lattice_stays_in_that_lattice():
+    """A NaN planted in one lattice of a batch: the other lattices still equal
+    their results alone, bitwise, and only the poisoned one reports a
+    non-finite population."""
+    from paper_1507_07294_amd import mplb
+    print("\n[case] NaN isolation in step_many", flush=True)
+    ws = [wl.perturbed_case(s, (0, 0, 1), 95 + i, coupled=True) for i, s in
+          enumerate([(16, 14, 12), (20, 10, 18), (12, 12, 12)])]
+    alone = []
+    for w in ws:
+        g = mplb.from_workload(w, "f32")
+        g.step(9)
+        alone.append({k: g.read(k) for k in ("phi", "ux", "p")})
+        g.destroy()
+    mix = [mplb.from_workload(w, "f32") for w in ws]
+    mix[1].poke(1, 7, 3 + 20 * 5, float("nan"))
+    mplb.mplb_step_many(mix, 9)
+    for i in (0, 2):
+        for k, v in alone[i].items():
+            assert np.array_equal(mix[i].read(k), v), (i, k)
+        rc, _ = mix[i].try_totals()
+        assert rc == 0
+    rc, _ = mix[1].try_totals()
+    assert rc == mplb.MPLB_E_NONFINITE
+    for g in mix:
+        g.destroy()
