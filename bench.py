@@ -116,7 +116,14 @@ def cpu_baseline(W, target_s=12.0, single_s=6.0):
         m1, s1, t1, d1 = sample(max(4, W // 32), single_s)
     finally:
         orc.set_threads(cores)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), model)
+    except OSError:
+        pass
     return {"value": round(mlups, 3), "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "host": {"cpu_model": model, "nproc": os.cpu_count()},
             "sample": f"{dims} z-slab through the interface of the W={W} Rayleigh-Taylor box, "
                       f"{steps} FP64 steps, {secs:.1f} s",
             "single_thread": {"value": round(m1, 3), "unit": "MLUPS", "cores": 1,
