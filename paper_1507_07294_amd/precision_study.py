@@ -7,7 +7,10 @@ error (the FP64 GPU path itself matches the FP64 oracle to 1e-12 on boxes the
 oracle can run).  One JSON line is printed per checkpoint and precision:
 
     python -m paper_1507_07294_amd.precision_study --W 128 --Re 256 \\
-        --checkpoints 1000,3200,6400 --precisions f32,f16,bf16
+        --checkpoints 1000,3200,6400 --precisions f32,f16,bf16 [--q 19]
+
+`--q 19` runs the D3Q19 variant of the Navier-Stokes lattice instead of the
+paper's D3Q15.
 
 Integral quantities: total phi drift relative to sum |phi_0|, kinetic energy
 (1/2) sum rho |u|^2, and the spike tip and bubble front (lowest and highest
@@ -42,9 +45,10 @@ def kinetic_energy(lt):
     return 0.5 * e
 
 
-def run(W, Re, checkpoints, precisions, log=print):
+def run(W, Re, checkpoints, precisions, log=print, q=15):
     import torch
     w = wl.rayleigh_taylor(W=W, Re=Re)
+    w.nse_q = q  # lattice of the Navier-Stokes populations
     names = ["f64"] + [p for p in precisions if p != "f64"]
     lats = {p: mplb.from_workload(w, p) for p in names}
     for lt in lats.values():
@@ -62,7 +66,7 @@ def run(W, Re, checkpoints, precisions, log=print):
             try:
                 lt.step(n - done)
             except mplb.MplbError as e:  # a precision that diverges is reported and dropped
-                log(json.dumps({"W": W, "Re": Re, "n": n, "precision": p, "diverged": str(e)}))
+                log(json.dumps({"W": W, "Re": Re, "q": q, "n": n, "precision": p, "diverged": str(e)}))
                 if p == "f64":  # no reference left
                     for other in lats.values():
                         other.destroy()
@@ -75,7 +79,7 @@ def run(W, Re, checkpoints, precisions, log=print):
         done = n
         ref = {f: lats["f64"].read(f) for f in FIELDS}
         for p, lt in lats.items():
-            row = {"W": W, "Re": Re, "n": n, "precision": p,
+            row = {"W": W, "Re": Re, "q": q, "n": n, "precision": p,
                    "MLUPS_segment": round(w.nodes * (n - prev) / secs[p] / 1e6, 1)}
             if p != "f64":
                 row["rel_l2_vs_f64"] = {f: float(f"{rel_l2(lt.read(f), ref[f]):.3e}") for f in FIELDS}
@@ -97,12 +101,13 @@ def main(argv=None):
     ap.add_argument("--Re", type=float, default=256.0)
     ap.add_argument("--checkpoints", default="1000,3200,6400")
     ap.add_argument("--precisions", default="f32,f16,bf16")
+    ap.add_argument("--q", type=int, default=15, choices=(15, 19), help="NSE lattice: D3Q15 or D3Q19")
     args = ap.parse_args(argv)
     cps = [int(v) for v in args.checkpoints.split(",") if v]
     if cps != sorted(cps) or not cps or cps[0] < 1:
         ap.error("checkpoints must be increasing and positive")
     run(args.W, args.Re, cps, [p for p in args.precisions.split(",") if p],
-        log=lambda s: print(s, flush=True))
+        log=lambda s: print(s, flush=True), q=args.q)
     return 0
 
 
