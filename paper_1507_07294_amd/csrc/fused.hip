@@ -2,8 +2,9 @@
 // (coupled D3Q7 + D3Q15, and the CHE-only D3Q7 variant), z-marching with
 // LDS rings.
 //
-// A block owns a 64 x TY column of nodes and marches along z through a
-// segment [z0, z1).  At plane z it
+// A block owns a 64 x TY column of nodes (TY = 16 for the coupled step with
+// FP32 populations, else 8) and marches along z through a segment [z0, z1).
+// At plane z it
 //   (a) issues the pulls of the seven f populations of plane z+3 on the tile
 //       plus a halo of two nodes,
 //   (b) while they are in flight, evaluates mu (Eqs. 2, 36) of plane z+1 on
@@ -741,19 +742,26 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
   return o;
 }
 
-#ifndef MPLB_TILE_Y
-#define MPLB_TILE_Y 8
-#endif
-constexpr int kTY = MPLB_TILE_Y;
+// Rows per tile: 8 (512 threads, two blocks per CU) except for the coupled
+// step with FP32 populations, which takes 16 (1024 threads, one block per CU).
+// There the halo of the phi ring falls from 59 % to 33 % of the tile's own
+// f pulls, and the step is 3 % faster on D3Q15 and 5 % on D3Q19 (same bits).
+// The 16-bit steps wait on memory latency and lose 11 % with one block per
+// CU; FP64 does not fit the 160 KB of LDS at 16 rows.
+constexpr int kTY = 8;
+template <int P>
+constexpr int coupled_ty() { return P == MPLB_F32 ? 16 : kTY; }
 
-// Segment length along z: enough blocks to fill the chip several times over,
-// but long segments where possible (each segment re-reads a few planes).
+// Segment length along z: enough blocks for a few rounds over the 256 CUs
+// (four rounds at two 8-row blocks per CU, two at one 16-row block), but long
+// segments where possible (each segment re-reads a few planes).
 Tiling make_tiling(const Geo& G, int TY, int min_lz) {
   Tiling t;
   t.tiles_x = (G.nx + kTX - 1) / kTX;
   t.tiles_y = (G.ny + TY - 1) / TY;
   int cols = t.tiles_x * t.tiles_y;
-  int want = (2048 + cols - 1) / cols;
+  int target = TY >= 16 ? 512 : 2048;
+  int want = (target + cols - 1) / cols;
   int lz = (G.nz + want - 1) / want;
   if (lz < min_lz) lz = min_lz;
   if (lz > G.nz) lz = G.nz;
@@ -771,12 +779,13 @@ template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s) {
   if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
-    Tiling tl = make_tiling(G, kTY, 16);
+    constexpr int TY = coupled_ty<P>();
+    Tiling tl = make_tiling(G, TY, 16);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     if (mode == MPLB_COUPLED)
-      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 15, V>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur, tl);
+      hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 15, V>), grid, dim3(kTX * TY), 0, s, G, C, B, cur, tl);
     else  // D3Q19: its forcing is Gamma T, so only the stencil switch applies
-      hipLaunchKernelGGL((k_fused<P, kTY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B,
+      hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * TY), 0, s, G, C, B,
                          cur, tl);
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
