@@ -71,6 +71,7 @@ def test_coupled_f64(shape, bc, seed):
     ((70, 37, 29), (0, 0, 1), 12),
     ((9, 10, 11), (1, 1, 1), 13),   # walls on every axis (the x/y-wall instantiation)
     ((33, 5, 40), (0, 0, 0), 14),   # fully periodic, thin in y
+    ((67, 35, 21), (1, 1, 0), 15),  # walls on x and y; 16-row tiles 16+16+3, x tail 3, two z segments
 ])
 def test_coupled_f32(shape, bc, seed):
     """FP32 against the oracle on the geometries of the FP64 test, less the
@@ -95,8 +96,9 @@ def test_coupled_q19_f64(shape, bc, seed):
     _compare(w, [1, 10, 60], "f64", F64_TOL)
 
 
-def test_coupled_q19_f32():
-    w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 44, coupled=True)
+@pytest.mark.parametrize("shape,bc,seed", [((24, 20, 18), (0, 0, 1), 44), ((67, 35, 21), (1, 1, 0), 48)])
+def test_coupled_q19_f32(shape, bc, seed):
+    w = wl.perturbed_case(shape, bc, seed, coupled=True)
     w.nse_q = 19
     _compare(w, [1, 10, 100], "f32", F32_TOL)
 
