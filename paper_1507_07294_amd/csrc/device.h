@@ -501,7 +501,12 @@ __device__ inline void collide_ns(const Coef<T>& C, T g[15], const Macro<T>& M) 
 //   g* = g^eq + T/2 - (lambda - 1) Gamma^-1 P Gamma (g - g^eq + T/2),
 // P the projector on the stress moments: only those five moments are formed.
 // g^eq from Eqs. 21-22, T from Eq. 28 (F = F_s + F_a + G), both in velocity
-// space.
+// space.  Velocities come in antipodal pairs (i, i+1), c_{i+1} = -c_i, so per
+// pair with s_i = E + O (E even, O odd in c):
+//   g^eq = G0 +- rho O,  T = Te +- To,
+// and the stress-moment weights, quadratic in c, are the same for both: the
+// pair enters the moments through (g_i + g_{i+1}) and takes one correction.
+// The rest population has no stress weight, so it is g^eq + T/2.
 template <class T>
 __device__ inline void collide_ns19(const Coef<T>& C, T g[19], const Macro<T>& M) {
   const T* u = M.u;
@@ -516,35 +521,50 @@ __device__ inline void collide_ns19(const Coef<T>& C, T g[19], const Macro<T>& M
     uAF += u[a] * AF[a];
     uF += u[a] * F[a];
   }
-  T base[19], m9 = 0, m11 = 0, m13 = 0, m14 = 0, m15 = 0;
+  {
+    const T w = (T)(1.0 / 3.0);
+    const T s0 = w * ((T)-1.5 * uu);
+    const T T0 = 3 * (s0 * (-uAF) + w * (-uF));
+    g[0] = 3 * p * (w - 1) + rho * s0 + T0 / 2;
+  }
+  T m9 = 0, m11 = 0, m13 = 0, m14 = 0, m15 = 0;
+  T be[9], bo[9];
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int k = 0; k < 9; ++k) {
+    const int i = 2 * k + 1;
     const int cx = c19(i, 0), cy = c19(i, 1), cz = c19(i, 2);
-    const T w = i == 0 ? (T)(1.0 / 3.0) : (i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0));
+    const T w = i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0);
     const T cu = cx * u[0] + cy * u[1] + cz * u[2];
-    const T si = w * (3 * cu + (T)4.5 * cu * cu - (T)1.5 * uu);
-    const T geq = 3 * p * (i == 0 ? w - 1 : w) + rho * si;
+    const T E = w * ((T)4.5 * cu * cu - (T)1.5 * uu);
+    const T O = 3 * w * cu;
     const T cAF = cx * AF[0] + cy * AF[1] + cz * AF[2];
     const T cF = cx * F[0] + cy * F[1] + cz * F[2];
-    const T Ti = 3 * (si * (cAF - uAF) + w * (cF - uF));
-    base[i] = geq + Ti / 2;
-    const T d = g[i] - base[i] + Ti;  // g - g^eq + T/2
+    const T G0 = 3 * p * w + rho * E;
+    const T Te = 3 * (O * cAF - E * uAF - w * uF);
+    const T To = 3 * (E * cAF - O * uAF + w * cF);
+    be[k] = G0 + Te / 2;  // g^eq + T/2 of the pair: be +- bo
+    bo[k] = rho * O + To / 2;
+    // d = g - g^eq + T/2 summed over the pair
+    const T dsum = (g[i] + g[i + 1]) - 2 * (G0 - Te / 2);
     const int c2 = cx * cx + cy * cy + cz * cz;
-    m9 += (3 * cx * cx - c2) * d;
-    m11 += (cy * cy - cz * cz) * d;
-    m13 += (cx * cy) * d;
-    m14 += (cy * cz) * d;
-    m15 += (cx * cz) * d;
+    m9 += (3 * cx * cx - c2) * dsum;
+    m11 += (cy * cy - cz * cz) * dsum;
+    m13 += (cx * cy) * dsum;
+    m14 += (cy * cz) * dsum;
+    m15 += (cx * cz) * dsum;
   }
-  const T k = C.lg[9] - 1;
-  const T b9 = k * m9 * (T)(1.0 / 36.0), b11 = k * m11 * (T)(1.0 / 12.0);
-  const T b13 = k * m13 / 4, b14 = k * m14 / 4, b15 = k * m15 / 4;
+  const T kl = C.lg[9] - 1;
+  const T b9 = kl * m9 * (T)(1.0 / 36.0), b11 = kl * m11 * (T)(1.0 / 12.0);
+  const T b13 = kl * m13 / 4, b14 = kl * m14 / 4, b15 = kl * m15 / 4;
 #pragma unroll
-  for (int i = 0; i < 19; ++i) {
+  for (int k = 0; k < 9; ++k) {
+    const int i = 2 * k + 1;
     const int cx = c19(i, 0), cy = c19(i, 1), cz = c19(i, 2);
     const int c2 = cx * cx + cy * cy + cz * cz;
-    g[i] = base[i] - ((3 * cx * cx - c2) * b9 + (cy * cy - cz * cz) * b11 + (cx * cy) * b13 + (cy * cz) * b14 +
-                      (cx * cz) * b15);
+    const T corr = (3 * cx * cx - c2) * b9 + (cy * cy - cz * cz) * b11 + (cx * cy) * b13 + (cy * cz) * b14 +
+                   (cx * cz) * b15;
+    g[i] = (be[k] + bo[k]) - corr;
+    g[i + 1] = (be[k] - bo[k]) - corr;
   }
 }
 
