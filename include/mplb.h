@@ -91,7 +91,9 @@ typedef struct mplb_params {
   double s_f[7];       /* S^f (Eq. 10), each in (0,2), s_1 = s_2 = s_3 */
   double nu;           /* kinematic viscosity > 0 (Eq. 33): lambda_9..13 = 1/(3 nu + 1/2) */
   double lambda_g[15]; /* S^g (Eq. 26), each in (0,2); entries 9..13 are replaced from nu
-                          unless lambda_override */
+                          unless lambda_override.  With every other entry 1 (the paper's
+                          rates) the D3Q15 step forms only the five stress moments of g;
+                          otherwise the full moment transform (same result up to rounding) */
   double gravity[3];   /* body acceleration; G = (rho - rho_ref) gravity */
   double rho_ref;      /* reference density of the body force (0: G = rho gravity) */
   /* study switches; 0 selects the readings used by default.  The switches are
@@ -186,8 +188,10 @@ int mplb_front(mplb_t* h, double out[2]);
  * its shape.  Each lattice computes exactly what mplb_step computes for it.
  * All handles must be initialised, share one precision and mode, and use the
  * first handle's stream.  Not thread-safe across calls on one device.
- * CHE-only and D3Q19 lattices, and lattices with a study switch set, are
- * stepped one after another (the batched kernel is the default D3Q15 step). */
+ * CHE-only and D3Q19 lattices, lattices with a study switch set, and a batch
+ * in which some lattices have S^g = 1 off the stress moments and others not,
+ * are stepped one after another (the batched kernel is the default D3Q15 step
+ * in one collision form). */
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
 
 /* Whether mplb_step_many replays its steps as a graph (enable != 0, the

@@ -455,6 +455,9 @@ constexpr int waves_per_eu() { return P == MPLB_F64 ? 2 : 4; }
 // carry no code for them: D3Q7 finite differences (Eqs. 35-36), and Gamma T
 // of Eq. 28 in place of the printed Eq. 32.  Built for FP64 and FP32 storage.
 constexpr int kVarS7 = 1, kVarF28 = 2;
+// S^g = 1 off the stress moments (the host sets it from the rates; any
+// precision): the D3Q15 collision forms only the stress moments of g
+constexpr int kVarUnit = 4;
 
 // The coupled step of logical block lb of one lattice (NT: streaming stores;
 // Q: velocities of the NSE lattice, 15 or 19; V: study variant bits).
@@ -607,7 +610,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
     if constexpr (Q == 19) collide_ns19(C, g, M);
-    else collide_ns<(V & kVarF28) != 0>(C, g, M);
+    else collide_ns<(V & kVarF28) != 0, (V & kVarUnit) != 0>(C, g, M);
     using S0 = typename L::S0;
     using S = typename L::S;
     if constexpr (PACK) __builtin_amdgcn_s_setprio(1);
@@ -642,7 +645,7 @@ k_fused(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
 // its (XCD-remapped) index and runs the same body as k_fused, so each
 // lattice computes exactly what it computes alone.  Buffer parity of item i
 // is cur0 ^ flip.
-template <int P, int TY, bool XYWALL, bool NT>
+template <int P, int TY, bool XYWALL, bool NT, int V = 0>
 __global__ void __launch_bounds__(kTX* TY) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused_many(const BatchItem<typename Prec<P>::T>* __restrict__ tab, int count, int flip) {
   const int b = logical_block(blockIdx.x, gridDim.x);
@@ -653,7 +656,7 @@ k_fused_many(const BatchItem<typename Prec<P>::T>* __restrict__ tab, int count, 
     else hi = mid - 1;
   }
   const BatchItem<typename Prec<P>::T> it = tab[lo];
-  fused_body<P, TY, XYWALL, NT>(it.G, it.C, it.B, it.cur0 ^ flip, it.TL, b - it.block0);
+  fused_body<P, TY, XYWALL, NT, 15, V>(it.G, it.C, it.B, it.cur0 ^ flip, it.TL, b - it.block0);
 }
 
 // CHE-only: mu is needed at the node only, so phi needs a halo of one and a
@@ -749,6 +752,7 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
   for (int i = 0; i < 15; ++i) o.lg[i] = (T)c.lg[i];
   o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
   o.stencil7 = c.stencil7; o.forcing28 = c.forcing28;
+  o.unit_rates = c.unit_rates;
   return o;
 }
 
@@ -811,16 +815,20 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
 template <int P, bool XYWALL, bool NT>
 hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s) {
-  const int v = (C.stencil7 ? kVarS7 : 0) | (C.forcing28 ? kVarF28 : 0);
+  const int v = (C.stencil7 ? kVarS7 : 0) | (C.forcing28 ? kVarF28 : 0) | (C.unit_rates ? kVarUnit : 0);
   if (v == 0) return fused_impl4<P, XYWALL, NT, 0>(mode, G, C, B, cur, s);
+  if (v == kVarUnit) return fused_impl4<P, XYWALL, NT, kVarUnit>(mode, G, C, B, cur, s);
   if constexpr (P == MPLB_F64 || P == MPLB_F32) {
     switch (v) {
       case kVarS7: return fused_impl4<P, XYWALL, NT, kVarS7>(mode, G, C, B, cur, s);
+      case kVarS7 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarUnit>(mode, G, C, B, cur, s);
       case kVarF28: return fused_impl4<P, XYWALL, NT, kVarF28>(mode, G, C, B, cur, s);
-      default: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28>(mode, G, C, B, cur, s);
+      case kVarF28 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarF28 | kVarUnit>(mode, G, C, B, cur, s);
+      case kVarS7 | kVarF28: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28>(mode, G, C, B, cur, s);
+      default: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28 | kVarUnit>(mode, G, C, B, cur, s);
     }
   }
-  return hipErrorInvalidValue;  // the study variants are built for FP64 and FP32 storage
+  return hipErrorInvalidValue;  // the study switches are built for FP64 and FP32 storage
 }
 
 template <int P, bool XYWALL>
@@ -838,17 +846,17 @@ hipError_t fused_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs
   return fused_impl2<P, false>(mode, G, C, B, cur, s);
 }
 
-template <int P, bool XYWALL, bool NT>
+template <int P, bool XYWALL, bool NT, int V>
 hipError_t many_impl2(const void* dtab, int count, int total_blocks, int flip, hipStream_t s) {
   using T = typename Prec<P>::T;
-  hipLaunchKernelGGL((k_fused_many<P, kTY, XYWALL, NT>), dim3((unsigned)total_blocks), dim3(kTX * kTY), 0, s,
+  hipLaunchKernelGGL((k_fused_many<P, kTY, XYWALL, NT, V>), dim3((unsigned)total_blocks), dim3(kTX * kTY), 0, s,
                      (const BatchItem<T>*)dtab, count, flip);
   return hipGetLastError();
 }
 
 // nsteps batched steps as a chain of kernel nodes (flip alternating), built
 // directly rather than by stream capture so that it works on any stream.
-template <int P, bool XYWALL, bool NT>
+template <int P, bool XYWALL, bool NT, int V>
 hipError_t many_graph2(const void* dtab, int count, int total_blocks, int nsteps, hipGraph_t* out) {
   hipGraph_t g = nullptr;
   hipError_t e = hipGraphCreate(&g, 0);
@@ -859,7 +867,7 @@ hipError_t many_graph2(const void* dtab, int count, int total_blocks, int nsteps
     const void* tab = dtab;
     void* args[] = {(void*)&tab, (void*)&count, (void*)&flip};
     hipKernelNodeParams kp{};
-    kp.func = (void*)k_fused_many<P, kTY, XYWALL, NT>;
+    kp.func = (void*)k_fused_many<P, kTY, XYWALL, NT, V>;
     kp.gridDim = dim3((unsigned)total_blocks);
     kp.blockDim = dim3(kTX * kTY);
     kp.sharedMemBytes = 0;
@@ -920,13 +928,18 @@ int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>
   }
 }
 
-hipError_t launch_fused_many(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks, int flip,
-                             hipStream_t s) {
-#define MPLB_MANY(PP)                                                                                     \
-  if (xywall) return nt ? many_impl2<PP, true, true>(dtab, count, total_blocks, flip, s)                \
-                        : many_impl2<PP, true, false>(dtab, count, total_blocks, flip, s);             \
-  return nt ? many_impl2<PP, false, true>(dtab, count, total_blocks, flip, s)                          \
-            : many_impl2<PP, false, false>(dtab, count, total_blocks, flip, s);
+hipError_t launch_fused_many(int P, bool xywall, bool nt, bool unit, const void* dtab, int count, int total_blocks,
+                             int flip, hipStream_t s) {
+#define MPLB_MANY_V(PP, W, N)                                                                        \
+  return unit ? many_impl2<PP, W, N, kVarUnit>(dtab, count, total_blocks, flip, s)                  \
+              : many_impl2<PP, W, N, 0>(dtab, count, total_blocks, flip, s);
+#define MPLB_MANY(PP)                                                                                \
+  if (xywall) {                                                                                      \
+    if (nt) MPLB_MANY_V(PP, true, true)                                                              \
+    MPLB_MANY_V(PP, true, false)                                                                     \
+  }                                                                                                  \
+  if (nt) MPLB_MANY_V(PP, false, true)                                                               \
+  MPLB_MANY_V(PP, false, false)
   switch (P) {
     case MPLB_F64: MPLB_MANY(MPLB_F64)
     case MPLB_F32: MPLB_MANY(MPLB_F32)
@@ -935,15 +948,21 @@ hipError_t launch_fused_many(int P, bool xywall, bool nt, const void* dtab, int 
     default: return hipErrorInvalidValue;
   }
 #undef MPLB_MANY
+#undef MPLB_MANY_V
 }
 
-hipError_t build_fused_many_graph(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks,
-                                  int nsteps, hipGraph_t* out) {
-#define MPLB_GRAPH(PP)                                                                                  \
-  if (xywall) return nt ? many_graph2<PP, true, true>(dtab, count, total_blocks, nsteps, out)         \
-                        : many_graph2<PP, true, false>(dtab, count, total_blocks, nsteps, out);      \
-  return nt ? many_graph2<PP, false, true>(dtab, count, total_blocks, nsteps, out)                    \
-            : many_graph2<PP, false, false>(dtab, count, total_blocks, nsteps, out);
+hipError_t build_fused_many_graph(int P, bool xywall, bool nt, bool unit, const void* dtab, int count,
+                                  int total_blocks, int nsteps, hipGraph_t* out) {
+#define MPLB_GRAPH_V(PP, W, N)                                                                       \
+  return unit ? many_graph2<PP, W, N, kVarUnit>(dtab, count, total_blocks, nsteps, out)             \
+              : many_graph2<PP, W, N, 0>(dtab, count, total_blocks, nsteps, out);
+#define MPLB_GRAPH(PP)                                                                               \
+  if (xywall) {                                                                                      \
+    if (nt) MPLB_GRAPH_V(PP, true, true)                                                             \
+    MPLB_GRAPH_V(PP, true, false)                                                                    \
+  }                                                                                                  \
+  if (nt) MPLB_GRAPH_V(PP, false, true)                                                              \
+  MPLB_GRAPH_V(PP, false, false)
   switch (P) {
     case MPLB_F64: MPLB_GRAPH(MPLB_F64)
     case MPLB_F32: MPLB_GRAPH(MPLB_F32)
@@ -952,6 +971,7 @@ hipError_t build_fused_many_graph(int P, bool xywall, bool nt, const void* dtab,
     default: return hipErrorInvalidValue;
   }
 #undef MPLB_GRAPH
+#undef MPLB_GRAPH_V
 }
 
 size_t fused_stream_threshold() { return kStreamBytes; }

@@ -23,13 +23,14 @@ size_t fused_batch_item_bytes(int P);
 int fused_batch_fill(int P, void* table, int i, const Geo& G, const Coef<double>& C, const Bufs& B, int cur0,
                      int block0);
 // (nt: streaming stores, for batches whose step moves more than
-// kStreamBytes; see fused_step_bytes)
-hipError_t launch_fused_many(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks, int flip,
-                             hipStream_t s);
+// kStreamBytes; see fused_step_bytes; unit: every item has S^g = 1 off the
+// stress moments, the form its lattice uses alone)
+hipError_t launch_fused_many(int P, bool xywall, bool nt, bool unit, const void* dtab, int count, int total_blocks,
+                             int flip, hipStream_t s);
 // the same for nsteps steps (flip = k & 1 at step k) as a graph of kernel
 // nodes; the caller instantiates, launches and destroys it
-hipError_t build_fused_many_graph(int P, bool xywall, bool nt, const void* dtab, int count, int total_blocks,
-                                  int nsteps, hipGraph_t* out);
+hipError_t build_fused_many_graph(int P, bool xywall, bool nt, bool unit, const void* dtab, int count,
+                                  int total_blocks, int nsteps, hipGraph_t* out);
 // algorithmic bytes one step of an N-node lattice moves (populations and
 // history read and written once)
 size_t fused_step_bytes(int P, int mode, long long N);

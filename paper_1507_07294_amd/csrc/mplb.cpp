@@ -252,6 +252,9 @@ int mplb_set_params(mplb_t* h, const mplb_params* p) {
   for (int i = 0; i < 15; ++i) C.lg[i] = (i >= 9 && i <= 13) ? 1.0 / tau_g : p->lambda_g[i];
   for (int i = 0; i < 15; ++i)
     if (!in02(C.lg[i])) return fail(h, MPLB_E_INVAL, "lambda[%d] outside (0,2)", i);
+  C.unit_rates = 1;
+  for (int i = 0; i < 15; ++i)
+    if ((i < 9 || i > 13) && C.lg[i] != 1.0) C.unit_rates = 0;
   h->have_params = true;
   return MPLB_OK;
 }
@@ -399,9 +402,10 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
 }
 
 // Instantiated graph of a chunk of batched steps, reused while the batch
-// keeps its shape (precision, walls, item count, block count, steps, table).
+// keeps its shape (precision, walls, collision form, item count, block count,
+// steps, table).
 struct ChunkGraph {
-  int prec = -1, xywall = 0, nt = 0, count = 0, blocks = 0, nsteps = 0;
+  int prec = -1, xywall = 0, nt = 0, unit = 0, count = 0, blocks = 0, nsteps = 0;
   const void* table = nullptr;
   hipGraphExec_t exec = nullptr;
   unsigned long long used = 0;
@@ -436,11 +440,12 @@ int mplb_set_step_many_graphs(int enable) {
 
 // The cached graph for this chunk shape, built and instantiated on a miss
 // (replacing the least recently used entry).
-static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, int count, int blocks, int nsteps,
-                       hipGraphExec_t* out) {
+static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, bool unit, int count, int blocks,
+                       int nsteps, hipGraphExec_t* out) {
   ChunkGraph* slot = nullptr;
   for (auto& c : T.graphs)
-    if (c.exec && c.prec == h0->prec && c.xywall == (int)xywall && c.nt == (int)nt && c.count == count &&
+    if (c.exec && c.prec == h0->prec && c.xywall == (int)xywall && c.nt == (int)nt && c.unit == (int)unit &&
+        c.count == count &&
         c.blocks == blocks &&
         c.nsteps == nsteps && c.table == T.dev)
       slot = &c;
@@ -451,7 +456,7 @@ static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, int coun
     if (slot->exec) HIPCHK(h0, hipGraphExecDestroy(slot->exec));
     slot->exec = nullptr;
     hipGraph_t g = nullptr;
-    HIPCHK(h0, build_fused_many_graph(h0->prec, xywall, nt, T.dev, count, blocks, nsteps, &g));
+    HIPCHK(h0, build_fused_many_graph(h0->prec, xywall, nt, unit, T.dev, count, blocks, nsteps, &g));
     hipError_t e = hipGraphInstantiate(&slot->exec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
@@ -461,6 +466,7 @@ static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, int coun
     slot->prec = h0->prec;
     slot->xywall = xywall;
     slot->nt = nt;
+    slot->unit = unit;
     slot->count = count;
     slot->blocks = blocks;
     slot->nsteps = nsteps;
@@ -484,11 +490,16 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   }
   mplb_t* h0 = hs[0];
   hipStream_t s = h0->stream;
-  bool any_switch = false;
-  for (int i = 0; i < count; ++i) any_switch = any_switch || hs[i]->C.forcing28 || hs[i]->C.stencil7;
-  // CHE-only and D3Q19 lattices, and lattices with a study switch, step one
-  // after another (the batched kernel is the default D3Q15 step)
-  if (h0->mode != MPLB_COUPLED || any_switch) {
+  bool any_switch = false, mixed_rates = false;
+  for (int i = 0; i < count; ++i) {
+    any_switch = any_switch || hs[i]->C.forcing28 || hs[i]->C.stencil7;
+    mixed_rates = mixed_rates || hs[i]->C.unit_rates != h0->C.unit_rates;
+  }
+  const bool unit = h0->C.unit_rates != 0;
+  // CHE-only and D3Q19 lattices, lattices with a study switch, and a batch
+  // that mixes unit and other S^g rates (two collision forms) step one after
+  // another: the batched kernel is the default D3Q15 step in one form
+  if (h0->mode != MPLB_COUPLED || any_switch || mixed_rates) {
     for (int k = 0; k < nsteps; ++k)
       for (int i = 0; i < count; ++i) {
         int rc = enqueue_step(hs[i], s);
@@ -539,12 +550,12 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   HIPCHK(h0, hipEventRecord(T.uploaded, s));
   if (g_use_graphs && nsteps > 1) {
     hipGraphExec_t ex = nullptr;
-    int rc = chunk_graph(h0, T, xywall, nt, count, blocks, nsteps, &ex);
+    int rc = chunk_graph(h0, T, xywall, nt, unit, count, blocks, nsteps, &ex);
     if (rc) return rc;
     HIPCHK(h0, hipGraphLaunch(ex, s));
   } else {
     for (int k = 0; k < nsteps; ++k)
-      HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, T.dev, count, blocks, k & 1, s));
+      HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, unit, T.dev, count, blocks, k & 1, s));
   }
   HIPCHK(h0, hipEventRecord(T.done, s));
   bool check = false;

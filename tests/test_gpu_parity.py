@@ -331,6 +331,51 @@ def test_step_many_equals_single_runs():
             assert np.array_equal(ref[k], got[k]), k
 
 
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2)])
+@pytest.mark.parametrize("shape,bc,seed", [((70, 37, 29), (0, 0, 1), 81), ((9, 10, 11), (1, 1, 1), 82),
+                                           ((67, 35, 21), (1, 1, 0), 83)])
+def test_coupled_unit_rates(precision, tol, shape, bc, seed):
+    """S^g = 1 off the stress moments (the paper's rates): the D3Q15 step
+    then forms only the five stress moments of g.  Against the oracle's full
+    moment-space collision on the perturbed boxes (whose other cases draw
+    rates away from 1 and so take the full transform)."""
+    w = wl.perturbed_case(shape, bc, seed, coupled=True, ratio=3.0)
+    w.params = w.params.replace(lambda_g=(1.0,) * 15)
+    _compare(w, [1, 10, 100], precision, tol)
+
+
+def _unit(w):
+    w.params = w.params.replace(lambda_g=(1.0,) * 15)
+    return w
+
+
+@pytest.mark.parametrize("precision", ["f32", "f16"])
+def test_step_many_rate_forms(precision):
+    """Batches by collision form: all unit rates (the reduced form), all
+    other rates (the full form) on a batch of the same shape, so that the
+    graph cache must tell the two apart, and a batch mixing both, which
+    steps its lattices one after another.  Every lattice equals its run
+    alone bitwise."""
+    from paper_1507_07294_amd import mplb
+    shapes = [(16, 16, 16), (24, 12, 20)]
+    gen = [wl.perturbed_case(s, (0, 0, 1), 90 + i, coupled=True) for i, s in enumerate(shapes)]
+    uni = [_unit(wl.perturbed_case(s, (0, 0, 1), 90 + i, coupled=True)) for i, s in enumerate(shapes)]
+    assert all(w.params.lambda_g[1] != 1.0 for w in gen)
+
+    def alone(w):
+        g = helpers.gpu_for(w, precision)
+        g.step(8)
+        return helpers.fields_of(g)
+
+    for batch in (uni, gen, [uni[0], gen[1]]):
+        lats = [helpers.gpu_for(w, precision) for w in batch]
+        mplb.mplb_step_many(lats, 8)
+        for w, g in zip(batch, lats):
+            ref, got = alone(w), helpers.fields_of(g)
+            for k in ref:
+                assert np.array_equal(ref[k], got[k]), (w.name, k)
+
+
 @pytest.mark.parametrize("precision", ["f16", "bf16"])
 @pytest.mark.parametrize("shape,bc,seed", [
     ((24, 20, 18), (0, 0, 1), 81),  # walls in z
