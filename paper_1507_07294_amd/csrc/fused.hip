@@ -3,7 +3,8 @@
 // LDS rings.
 //
 // A block owns a 64 x TY column of nodes (TY = 16 for the coupled step with
-// FP32 populations, else 8) and marches along z through a segment [z0, z1).
+// FP32 populations on a lattice of at least 512 such blocks, else 8) and
+// marches along z through a segment [z0, z1).
 // At plane z it
 //   (a) issues the pulls of the seven f populations of plane z+3 on the tile
 //       plus a halo of two nodes,
@@ -757,7 +758,8 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
 }
 
 // Rows per tile: 8 (512 threads, two blocks per CU) except for the coupled
-// step with FP32 populations, which takes 16 (1024 threads, one block per CU).
+// step with FP32 populations on a large lattice, which takes 16 (1024
+// threads, one block per CU).
 // There the halo of the phi ring falls from 59 % to 33 % of the tile's own
 // f pulls, and the step is 3 % faster on D3Q15 and 5 % on D3Q19 (same bits).
 // The 16-bit steps wait on memory latency and lose 11 % with one block per
@@ -789,18 +791,36 @@ Tiling make_tiling(const Geo& G, int TY, int min_lz) {
 // 18 % slower for a 128^3 CHE-only box that stays cache-resident).
 constexpr size_t kStreamBytes = (size_t)512 << 20;
 
+// One coupled step with TY-row tiles.
+template <int P, int TY, bool XYWALL, bool NT, int V>
+void launch_coupled(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
+                    const Tiling& tl, hipStream_t s) {
+  dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
+  if (mode == MPLB_COUPLED)
+    hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 15, V>), grid, dim3(kTX * TY), 0, s, G, C, B, cur, tl);
+  else  // D3Q19: its forcing is Gamma T, so only the stencil switch applies
+    hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * TY), 0, s, G, C, B, cur,
+                       tl);
+}
+
+// 16-row tiles only on a lattice that fills two rounds of the chip with them:
+// on small lattices (64^3: 16 blocks) they halve the blocks that run at all,
+// and 8-row tiles took 26 % less time per step on the serving trace's boxes.
+constexpr int kMinBlocksTall = 512;
+
 template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s) {
   if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
     constexpr int TY = coupled_ty<P>();
-    Tiling tl = make_tiling(G, TY, 16);
-    dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
-    if (mode == MPLB_COUPLED)
-      hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 15, V>), grid, dim3(kTX * TY), 0, s, G, C, B, cur, tl);
-    else  // D3Q19: its forcing is Gamma T, so only the stencil switch applies
-      hipLaunchKernelGGL((k_fused<P, TY, XYWALL, NT, 19, V & kVarS7>), grid, dim3(kTX * TY), 0, s, G, C, B,
-                         cur, tl);
+    if constexpr (TY != kTY) {
+      Tiling tall = make_tiling(G, TY, 16);
+      if (tall.tiles_x * tall.tiles_y * tall.nseg >= kMinBlocksTall) {
+        launch_coupled<P, TY, XYWALL, NT, V>(mode, G, C, B, cur, tall, s);
+        return hipGetLastError();
+      }
+    }
+    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, 16), s);
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
