@@ -71,7 +71,7 @@ def test_coupled_f64(shape, bc, seed):
     ((70, 37, 29), (0, 0, 1), 12),
     ((9, 10, 11), (1, 1, 1), 13),   # walls on every axis (the x/y-wall instantiation)
     ((33, 5, 40), (0, 0, 0), 14),   # fully periodic, thin in y
-    ((67, 35, 21), (1, 1, 0), 15),  # walls on x and y; 16-row tiles 16+16+3, x tail 3, two z segments
+    ((67, 35, 21), (1, 1, 0), 15),  # walls on x and y; ragged x and y tails, two z segments
 ])
 def test_coupled_f32(shape, bc, seed):
     """FP32 against the oracle on the geometries of the FP64 test, less the
@@ -101,6 +101,20 @@ def test_coupled_q19_f32(shape, bc, seed):
     w = wl.perturbed_case(shape, bc, seed, coupled=True)
     w.nse_q = 19
     _compare(w, [1, 10, 100], "f32", F32_TOL)
+
+
+@pytest.mark.parametrize("q", [15, 19])
+def test_f32_tall_tiles_with_side_walls(q):
+    """The FP32 step takes 16-row tiles only on a lattice of at least 512 such
+    blocks.  65 x 17 x 2048 is the smallest kind of box that does: 2 x 2 tiles
+    of 64 x 16 (tails of one column and one row) times 128 segments of 16
+    planes = 512 blocks, 2.3M nodes.  Walls on x and y (the per-lane wall
+    instantiation), against the oracle after 1 and 4 steps."""
+    w = wl.perturbed_case((65, 17, 2048), (1, 1, 0), 49 + q, coupled=True)
+    w.nse_q = q
+    if q == 15:
+        w.params = w.params.replace(lambda_g=(1.0,) * 15)  # the paper's rates: the stress-moment form
+    _compare(w, [1, 4], "f32", F32_TOL)
 
 
 @pytest.mark.parametrize("precision", ["f16", "bf16"])
