@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -47,13 +48,25 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_source_hash():
-    """Hash of the sources of the step kernel; a traffic figure taken on other
-    sources is not reported."""
+def _code_of(text):
+    """C++ source without its comments and with runs of blank space folded:
+    an edit of a comment is not a change of the kernel."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
+def kernel_source_hash(read=None):
+    """Hash of the code of the step kernel's sources; a traffic figure taken on
+    other code is not reported.  `read(name)` returns a source's text (default:
+    the file in the package)."""
+    if read is None:
+        def read(name):
+            with open(os.path.join(ROOT, "paper_1507_07294_amd", "csrc", name), encoding="utf-8") as fh:
+                return fh.read()
     h = hashlib.sha256()
     for f in ("fused.hip", "device.h", "common.h"):
-        with open(os.path.join(ROOT, "paper_1507_07294_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        h.update(_code_of(read(f)).encode())
     return h.hexdigest()[:16]
 
 

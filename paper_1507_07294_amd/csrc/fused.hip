@@ -461,7 +461,8 @@ constexpr int kVarS7 = 1, kVarF28 = 2;
 constexpr int kVarUnit = 4;
 
 // The coupled step of logical block lb of one lattice (NT: streaming stores;
-// Q: velocities of the NSE lattice, 15 or 19; V: study variant bits).
+// Q: velocities of the NSE lattice, 15 or 19; V: variant bits, the study
+// switches and the collision form).
 template <int P, int TY, bool XYWALL, bool NT, int Q = 15, int V = 0>
 __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                                   const Tiling& TL, int lb) {
@@ -761,7 +762,7 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
 // step with FP32 populations on a large lattice, which takes 16 (1024
 // threads, one block per CU).
 // There the halo of the phi ring falls from 59 % to 33 % of the tile's own
-// f pulls, and the step is 3 % faster on D3Q15 and 5 % on D3Q19 (same bits).
+// f pulls, and the step is 3 % faster on D3Q15 and 4 % on D3Q19 (same bits).
 // The 16-bit steps wait on memory latency and lose 11 % with one block per
 // CU; FP64 does not fit the 160 KB of LDS at 16 rows.
 constexpr int kTY = 8;

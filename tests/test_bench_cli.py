@@ -25,3 +25,20 @@ def test_cpu_baseline_reports_the_oracle_and_its_threads():
     assert out["single_thread"]["cores"] == 1 and out["single_thread"]["value"] > 0
     assert "z-slab" in out["sample"]
     assert orc.threads() == out["cores"]  # thread count restored after the one-thread sample
+
+
+def test_kernel_hash_ignores_comments():
+    """A comment edit is not a kernel change: the traffic record keyed by the
+    code hash stays valid; a code edit is a change."""
+    import bench
+    a = "int f(int x) { // one\n  return x + 1; /* two\n lines */ }\n"
+    b = "int f(int x) {\n  // another comment\n  return x + 1;  }"
+    c = "int f(int x) { return x + 2; }"
+    assert bench._code_of(a) == bench._code_of(b) == "int f(int x) { return x + 1; }"
+    assert bench._code_of(c) != bench._code_of(a)
+    files = {"fused.hip": a, "device.h": "// h\n", "common.h": ""}
+    h1 = bench.kernel_source_hash(files.__getitem__)
+    files["fused.hip"] = b
+    assert bench.kernel_source_hash(files.__getitem__) == h1
+    files["fused.hip"] = c
+    assert bench.kernel_source_hash(files.__getitem__) != h1
