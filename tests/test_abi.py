@@ -55,6 +55,20 @@ def test_host_only_calls(lib):
         assert abs((q.value - r.value) - extra32 / 2) <= 2 * 256  # the same four arrays at 2 bytes
 
 
+def test_size_limit_boundary(lib):
+    """The kernels index a lattice with 32-bit node offsets: just under 2^31
+    nodes is accepted (here in 16-bit storage, which fits one GPU's HBM),
+    exactly 2^31 is refused, as is a plane of 2^29 nodes (in-plane byte
+    offsets of up to 8-byte elements must fit 32 bits)."""
+    n = C.c_size_t(0)
+    assert lib.mplb_required_bytes(2048, 1024, 1023, mplb.MPLB_F32_F16, mplb.MPLB_COUPLED, C.byref(n)) == 0
+    assert 2048 * 1024 * 1023 * 100 < n.value < 300 * 2 ** 30
+    assert lib.mplb_required_bytes(2048, 1024, 1024, mplb.MPLB_F32_F16, mplb.MPLB_COUPLED,
+                                   C.byref(n)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_required_bytes(1 << 15, 1 << 14, 1, mplb.MPLB_F32, mplb.MPLB_COUPLED,
+                                   C.byref(n)) == mplb.MPLB_E_INVAL
+
+
 def test_invalid_create_is_rejected_before_any_device_call(lib):
     h = C.c_void_p(1)
     bc = (C.c_int * 3)(0, 0, 5)
