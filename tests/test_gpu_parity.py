@@ -430,9 +430,10 @@ def test_full_size_sampled(precision, tol):
     _sampled_check(_full_size_case(), precision, tol)
 
 
-@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3)])
+@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2), ("f64", F64_TOL)])
 def test_full_size_sampled_d3q19(precision, tol):
-    """The same check for the D3Q19 variant of the NSE lattice."""
+    """The same check for the D3Q19 variant of the NSE lattice, in every
+    storage precision."""
     _sampled_check(dataclasses.replace(_full_size_case(), nse_q=19), precision, tol)
 
 
