@@ -509,21 +509,23 @@ def test_c2_che_only_full_field():
 C3_STEPS = 40
 
 
-@functools.lru_cache(maxsize=1)
-def _c3_oracle():
+@functools.lru_cache(maxsize=2)
+def _c3_oracle(q=15):
     w = wl.rayleigh_taylor(W=128, Re=256.0)
+    w.nse_q = q
     o = helpers.oracle_for(w)
     o.step(C3_STEPS)
     return w, helpers.fields_of(o, True)
 
 
+@pytest.mark.parametrize("q", [15, 19])
 @pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2)])
-def test_c3_full_field(precision, tol):
+def test_c3_full_field(precision, tol, q):
     """The 128 x 128 x 512 Rayleigh-Taylor box (Re = 256) with each storage
     precision, every node against the FP64 oracle after 40 steps; one oracle
-    run serves the three cases."""
-    print(f"\n[case] C3 full field 128x128x512 {precision} {C3_STEPS} steps", flush=True)
-    w, ref = _c3_oracle()
+    run per lattice (D3Q15, D3Q19) serves the three precisions."""
+    print(f"\n[case] C3 full field 128x128x512 D3Q{q} {precision} {C3_STEPS} steps", flush=True)
+    w, ref = _c3_oracle(q)
     g = helpers.gpu_for(w, precision)
     g.step(C3_STEPS)
     _full_field_check(w, helpers.fields_of(g, True), ref, precision, tol)
