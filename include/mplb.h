@@ -167,6 +167,13 @@ long mplb_step_count(const mplb_t* h);
  * out[N] (host, double).  Does not change the state. */
 int mplb_read(mplb_t* h, int field, double* out);
 
+/* The same field on the vertical plane x = y only (the diagonal section that
+ * Sec. III C shows for the Rayleigh-Taylor runs), into out[nz * nx] (host,
+ * double): out[z * nx + i] is the value at node (i, i, z).  Needs nx = ny
+ * (MPLB_E_INVAL otherwise); the plane is gathered on the device, so only
+ * nx * nz values cross PCIe.  Does not change the state; synchronises. */
+int mplb_read_diagonal(mplb_t* h, int field, double* out);
+
 /* FP64 totals at the current level: out[0] = sum phi, out[1..3] = sum of
  * sum_i c_i g_i, out[4..6] = sum of F_s + F_a + G.  Returns MPLB_E_NONFINITE
  * if any population is non-finite. */

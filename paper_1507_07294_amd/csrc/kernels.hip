@@ -462,6 +462,21 @@ hipError_t launch_front(int P, const Geo& G, const Bufs& B, hipStream_t s) {
   return hipGetLastError();
 }
 
+// The vertical plane x = y of a field with nx = ny (the diagonal section of a
+// Rayleigh-Taylor box): out[z * nx + i] = f(i, i, z).
+__global__ void __launch_bounds__(kBlock) k_diag(const double* __restrict__ f, double* __restrict__ out, int nx,
+                                                 int nz) {
+  const int t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= nx * nz) return;
+  const int i = t % nx, z = t / nx;
+  out[t] = f[((size_t)z * nx + i) * nx + i];
+}
+
+hipError_t launch_diag(const double* f, double* out, int nx, int nz, hipStream_t s) {
+  hipLaunchKernelGGL(k_diag, grid_for(nx * nz), dim3(kBlock), 0, s, f, out, nx, nz);
+  return hipGetLastError();
+}
+
 hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStream_t s) {
   if (P == MPLB_F64) hipLaunchKernelGGL(k_cvt_in<double>, grid_for(G.N), dim3(kBlock), 0, s, B.out, (double*)dst, G.N);
   else hipLaunchKernelGGL(k_cvt_in<float>, grid_for(G.N), dim3(kBlock), 0, s, B.out, (float*)dst, G.N);

@@ -45,6 +45,9 @@ hipError_t launch_totals(int P, int mode, const Geo& G, const Coef<double>& C, c
 // lowest and highest z where phi (the B.phi array) crosses 0 along z, into
 // B.red[kRedSlots*8 .. +2) (-1, -1 when there is none)
 hipError_t launch_front(int P, const Geo& G, const Bufs& B, hipStream_t s);
+// out[z * nx + i] = f[(z * nx + i) * nx + i]: the plane x = y of a field with
+// nx = ny (nx * nz elements; out must not overlap f)
+hipError_t launch_diag(const double* f, double* out, int nx, int nz, hipStream_t s);
 // dst[n] = (T) B.out[n] for n < N (upload of a host field staged in B.out)
 hipError_t launch_cvt_in(int P, const Geo& G, const Bufs& B, void* dst, hipStream_t s);
 // equilibrium initial state into buffer `cur`, from phi, mu and u (held in phiu)

@@ -592,6 +592,28 @@ int mplb_read(mplb_t* h, int field, double* out) {
   return MPLB_OK;
 }
 
+int mplb_read_diagonal(mplb_t* h, int field, double* out) {
+  if (!h || !out || field < MPLB_PHI || field > MPLB_P) return MPLB_E_INVAL;
+  if (h->G.nx != h->G.ny) return fail(h, MPLB_E_INVAL, "the plane x = y needs nx = ny");
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "read before init");
+  int rc = prepare_macro(h);
+  if (rc) return rc;
+  HIPCHK(h, launch_macro(h->prec, h->mode, h->G, h->C, h->B, h->cur, field, h->stream));
+  const size_t n = (size_t)h->G.nx * h->G.nz;
+  const double* src = h->B.out;
+  if (h->G.nx > 1) {
+    // gathered into the phi array, read-out scratch that every read forms
+    // anew (nx * nz doubles fit in its nx * nx * nz compute-precision words)
+    if (n * sizeof(double) > h->plan.phi) return fail(h, MPLB_E_INVAL, "plane larger than its staging");
+    double* d = (double*)h->B.phi;
+    HIPCHK(h, launch_diag(h->B.out, d, h->G.nx, h->G.nz, h->stream));
+    src = d;
+  }
+  HIPCHK(h, hipMemcpyAsync(out, src, n * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  return MPLB_OK;
+}
+
 int mplb_front(mplb_t* h, double out[2]) {
   if (!h || !out) return MPLB_E_INVAL;
   if (!h->have_init) return fail(h, MPLB_E_STATE, "front before init");

@@ -75,6 +75,7 @@ def lib():
             "mplb_set_check_interval": (C.c_int, [vp, C.c_int]),
             "mplb_step_count": (C.c_long, [vp]),
             "mplb_read": (C.c_int, [vp, C.c_int, dp]),
+            "mplb_read_diagonal": (C.c_int, [vp, C.c_int, dp]),
             "mplb_totals": (C.c_int, [vp, dp]),
             "mplb_front": (C.c_int, [vp, dp]),
             "mplb_step_many": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int]),
@@ -224,6 +225,15 @@ class Lattice:
     def read(self, field):
         out = np.empty(self.grid, dtype=np.float64)
         self._chk(lib().mplb_read(self._h, FIELDS[field] if isinstance(field, str) else int(field), _dp(out)))
+        return out
+
+    def read_diagonal(self, field):
+        """The field on the vertical plane x = y (nx = ny), shape (nz, nx):
+        [z, i] is the value at node (i, i, z); gathered on the device."""
+        nz, _, nx = self.grid
+        out = np.empty((nz, nx), dtype=np.float64)
+        self._chk(lib().mplb_read_diagonal(self._h, FIELDS[field] if isinstance(field, str) else int(field),
+                                           _dp(out)))
         return out
 
     def read_all(self):

@@ -55,6 +55,14 @@ def test_host_only_calls(lib):
         assert abs((q.value - r.value) - extra32 / 2) <= 2 * 256  # the same four arrays at 2 bytes
 
 
+def test_read_diagonal_rejects_bad_arguments_before_any_device_call(lib):
+    out = (C.c_double * 4)()
+    assert lib.mplb_read_diagonal(None, mplb.MPLB_PHI, out) == mplb.MPLB_E_INVAL
+    h = C.c_void_p(1)  # never dereferenced: the field check comes first
+    assert lib.mplb_read_diagonal(h, 99, out) == mplb.MPLB_E_INVAL
+    assert lib.mplb_read_diagonal(h, mplb.MPLB_PHI, None) == mplb.MPLB_E_INVAL
+
+
 def test_size_limit_boundary(lib):
     """The kernels index a lattice with 32-bit node offsets: just under 2^31
     nodes is accepted (here in 16-bit storage, which fits one GPU's HBM),

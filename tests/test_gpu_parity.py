@@ -301,6 +301,30 @@ def test_nonfinite_reported_with_step_index():
     assert rc == mplb.MPLB_E_NONFINITE
 
 
+@pytest.mark.parametrize("precision", ["f32", "f16", "f64"])
+def test_read_diagonal_is_the_x_equals_y_plane(precision):
+    """mplb_read_diagonal gathers the plane x = y on the device: bitwise the
+    nodes (i, i, z) of the full read, for every field; a 1 x 1 column is the
+    whole field; nx != ny is refused."""
+    from paper_1507_07294_amd import mplb
+    w = wl.rayleigh_taylor(W=32, Re=256.0)
+    g = helpers.gpu_for(w, precision)
+    g.step(20)
+    nz, ny, nx = g.grid
+    i = np.arange(nx)
+    for k in helpers.FIELDS:
+        full = g.read(k)
+        d = g.read_diagonal(k)
+        assert d.shape == (nz, nx)
+        assert np.array_equal(d, full[:, i, i]), k
+    col = helpers.gpu_for(wl.perturbed_case((1, 1, 48), (0, 0, 1), 5, coupled=True), precision)
+    col.step(3)
+    assert np.array_equal(col.read_diagonal("uz"), col.read("uz")[:, 0, :])
+    rect = helpers.gpu_for(wl.perturbed_case((24, 20, 18), (0, 0, 1), 6, coupled=True), precision)
+    with pytest.raises(mplb.MplbError):
+        rect.read_diagonal("phi")
+
+
 def test_checkpoint_restore_is_bitwise():
     w = wl.perturbed_case((20, 18, 16), (0, 0, 1), 51, coupled=True)
     a = helpers.gpu_for(w, "f32")
