@@ -156,10 +156,17 @@ int mplb_init(mplb_t* h, const double* phi0, const double* u0);
  * non-finite check (see mplb_set_check_interval) finds a NaN or Inf. */
 int mplb_step(mplb_t* h, int nsteps);
 
-/* Every k steps (k >= 1) mplb_step synchronises and checks that no
- * population became non-finite; k = 0 (default) checks only when
- * mplb_totals is called. */
+/* Every k steps (k >= 1) mplb_step and mplb_step_many synchronise and check
+ * that no population of the lattice became non-finite; k = 0 (default)
+ * checks only when mplb_totals or mplb_check_finite is called. */
 int mplb_set_check_interval(mplb_t* h, int k);
+
+/* Synchronise the handle's stream and return MPLB_E_NONFINITE if a
+ * population of this lattice has become NaN or Inf since mplb_init or
+ * mplb_restore (the step kernels raise a per-lattice flag that stays set),
+ * MPLB_OK otherwise.  Lets a caller of mplb_step_many find which lattices of
+ * a batch failed.  MPLB_E_STATE before init. */
+int mplb_check_finite(mplb_t* h);
 
 long mplb_step_count(const mplb_t* h);
 
@@ -198,7 +205,11 @@ int mplb_front(mplb_t* h, double out[2]);
  * CHE-only and D3Q19 lattices, lattices with a study switch set, and a batch
  * in which some lattices have S^g = 1 off the stress moments and others not,
  * are stepped one after another (the batched kernel is the default D3Q15 step
- * in one collision form). */
+ * in one collision form).  Afterwards every lattice whose own check interval
+ * (mplb_set_check_interval) was crossed is checked; all of them are checked
+ * even when one fails, each failed lattice's mplb_last_error names it, and
+ * the call returns MPLB_E_NONFINITE if any failed (the error text of hs[0]
+ * otherwise). */
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
 
 /* Whether mplb_step_many replays its steps as a graph (enable != 0, the
@@ -232,6 +243,14 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hi
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;
  * node n) of the current state with `value`, e.g. to plant a NaN. */
 int mplb_poke(mplb_t* h, int set, int i, long node, double value);
+
+/* Test hook: the tile height of this lattice's coupled step.  0 (default)
+ * lets mplb_step choose (16 rows for FP32 populations on a lattice that
+ * fills at least 512 such tiles, 8 otherwise); 8 or 16 forces one (16: FP32
+ * populations only, else MPLB_E_INVAL).  The tiling changes which work a
+ * block does, not the arithmetic of a node, so the fields are bitwise the
+ * same; mplb_step_many always uses 8 rows. */
+int mplb_force_tile_rows(mplb_t* h, int rows);
 
 void mplb_destroy(mplb_t* h);
 const char* mplb_last_error(const mplb_t* h);

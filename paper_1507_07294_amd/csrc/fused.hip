@@ -811,12 +811,12 @@ constexpr int kMinBlocksTall = 512;
 
 template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
-                       hipStream_t s) {
+                       hipStream_t s, int rows) {
   if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
     constexpr int TY = coupled_ty<P>();
     if constexpr (TY != kTY) {
       Tiling tall = make_tiling(G, TY, 16);
-      if (tall.tiles_x * tall.tiles_y * tall.nseg >= kMinBlocksTall) {
+      if (rows == TY || (rows == 0 && tall.tiles_x * tall.tiles_y * tall.nseg >= kMinBlocksTall)) {
         launch_coupled<P, TY, XYWALL, NT, V>(mode, G, C, B, cur, tall, s);
         return hipGetLastError();
       }
@@ -835,18 +835,18 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
 
 template <int P, bool XYWALL, bool NT>
 hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
-                       hipStream_t s) {
+                       hipStream_t s, int rows) {
   const int v = (C.stencil7 ? kVarS7 : 0) | (C.forcing28 ? kVarF28 : 0) | (C.unit_rates ? kVarUnit : 0);
-  if (v == 0) return fused_impl4<P, XYWALL, NT, 0>(mode, G, C, B, cur, s);
-  if (v == kVarUnit) return fused_impl4<P, XYWALL, NT, kVarUnit>(mode, G, C, B, cur, s);
+  if (v == 0) return fused_impl4<P, XYWALL, NT, 0>(mode, G, C, B, cur, s, rows);
+  if (v == kVarUnit) return fused_impl4<P, XYWALL, NT, kVarUnit>(mode, G, C, B, cur, s, rows);
   if constexpr (P == MPLB_F64 || P == MPLB_F32) {
     switch (v) {
-      case kVarS7: return fused_impl4<P, XYWALL, NT, kVarS7>(mode, G, C, B, cur, s);
-      case kVarS7 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarUnit>(mode, G, C, B, cur, s);
-      case kVarF28: return fused_impl4<P, XYWALL, NT, kVarF28>(mode, G, C, B, cur, s);
-      case kVarF28 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarF28 | kVarUnit>(mode, G, C, B, cur, s);
-      case kVarS7 | kVarF28: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28>(mode, G, C, B, cur, s);
-      default: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28 | kVarUnit>(mode, G, C, B, cur, s);
+      case kVarS7: return fused_impl4<P, XYWALL, NT, kVarS7>(mode, G, C, B, cur, s, rows);
+      case kVarS7 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarUnit>(mode, G, C, B, cur, s, rows);
+      case kVarF28: return fused_impl4<P, XYWALL, NT, kVarF28>(mode, G, C, B, cur, s, rows);
+      case kVarF28 | kVarUnit: return fused_impl4<P, XYWALL, NT, kVarF28 | kVarUnit>(mode, G, C, B, cur, s, rows);
+      case kVarS7 | kVarF28: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28>(mode, G, C, B, cur, s, rows);
+      default: return fused_impl4<P, XYWALL, NT, kVarS7 | kVarF28 | kVarUnit>(mode, G, C, B, cur, s, rows);
     }
   }
   return hipErrorInvalidValue;  // the study switches are built for FP64 and FP32 storage
@@ -854,17 +854,19 @@ hipError_t fused_impl3(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
 
 template <int P, bool XYWALL>
 hipError_t fused_impl2(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
-                       hipStream_t s) {
-  if (fused_step_bytes(P, mode, G.N) > kStreamBytes) return fused_impl3<P, XYWALL, true>(mode, G, C, B, cur, s);
-  return fused_impl3<P, XYWALL, false>(mode, G, C, B, cur, s);
+                       hipStream_t s, int rows) {
+  if (fused_step_bytes(P, mode, G.N) > kStreamBytes)
+    return fused_impl3<P, XYWALL, true>(mode, G, C, B, cur, s, rows);
+  return fused_impl3<P, XYWALL, false>(mode, G, C, B, cur, s, rows);
 }
 
 template <int P>
-hipError_t fused_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur, hipStream_t s) {
+hipError_t fused_impl(int mode, const Geo& G, const Coef<double>& Cd, const Bufs& B, int cur, hipStream_t s,
+                      int rows) {
   using T = typename Prec<P>::T;
   Coef<T> C = cast_coef_f<T>(Cd);
-  if (G.wall_x || G.wall_y) return fused_impl2<P, true>(mode, G, C, B, cur, s);
-  return fused_impl2<P, false>(mode, G, C, B, cur, s);
+  if (G.wall_x || G.wall_y) return fused_impl2<P, true>(mode, G, C, B, cur, s, rows);
+  return fused_impl2<P, false>(mode, G, C, B, cur, s, rows);
 }
 
 template <int P, bool XYWALL, bool NT, int V>
@@ -924,12 +926,12 @@ int batch_fill_impl(void* table, int i, const Geo& G, const Coef<double>& Cd, co
 }  // namespace
 
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
-                             hipStream_t s) {
+                             hipStream_t s, int rows) {
   switch (P) {
-    case MPLB_F64: return fused_impl<MPLB_F64>(mode, G, C, B, cur, s);
-    case MPLB_F32: return fused_impl<MPLB_F32>(mode, G, C, B, cur, s);
-    case MPLB_F32_F16: return fused_impl<MPLB_F32_F16>(mode, G, C, B, cur, s);
-    case MPLB_F32_BF16: return fused_impl<MPLB_F32_BF16>(mode, G, C, B, cur, s);
+    case MPLB_F64: return fused_impl<MPLB_F64>(mode, G, C, B, cur, s, rows);
+    case MPLB_F32: return fused_impl<MPLB_F32>(mode, G, C, B, cur, s, rows);
+    case MPLB_F32_F16: return fused_impl<MPLB_F32_F16>(mode, G, C, B, cur, s, rows);
+    case MPLB_F32_BF16: return fused_impl<MPLB_F32_BF16>(mode, G, C, B, cur, s, rows);
     default: return hipErrorInvalidValue;
   }
 }

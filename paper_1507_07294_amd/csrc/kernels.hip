@@ -129,7 +129,9 @@ template <int P, bool COUPLED, int Q = 15>
 __global__ void __launch_bounds__(kBlock) k_totals(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur) {
   using T = typename Prec<P>::T;
   double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int n = blockIdx.x * kBlock + threadIdx.x; n < G.N; n += gridDim.x * kBlock) {
+  // 64-bit stride: the last node plus one stride can pass INT_MAX
+  for (long long nl = (long long)blockIdx.x * kBlock + threadIdx.x; nl < G.N; nl += (long long)gridDim.x * kBlock) {
+    const int n = (int)nl;
     Macro<T> M;
     bool ok = node_macro<P, COUPLED, Q>(G, C, B, cur, n, M);
     acc[0] += (double)M.phi;

@@ -12,9 +12,10 @@ hipError_t launch_phi(int P, int mode, const Geo& G, const Bufs& B, int cur, hip
 // mu from phi (Eqs. 2, 36)
 hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, hipStream_t s);
 // one step as a single z-marching kernel (fused.hip): reads buffer `cur`,
-// writes buffer 1 - cur
+// writes buffer 1 - cur.  rows: tile height of the coupled step, 0 for the
+// automatic choice, 8 or 16 to force one (16: FP32 populations only)
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
-                             hipStream_t s);
+                             hipStream_t s, int rows = 0);
 // Batched coupled step over a device table of BatchItem<T> (T of P):
 // fused_batch_item_bytes gives the item size, fused_batch_fill writes item i
 // of a host table and returns that lattice's block count, launch_fused_many

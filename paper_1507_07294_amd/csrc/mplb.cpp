@@ -1,6 +1,7 @@
 // Host side of libmplb: the C-ABI declared in include/mplb.h.
 #include <hip/hip_runtime.h>
 
+#include <climits>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -56,18 +57,22 @@ Plan make_plan(long long N, int prec, int mode) {
   return p;
 }
 
-// Node indices are 32-bit, and the step kernel forms in-plane byte offsets
-// in 32 bits (nx*ny elements of up to 8 bytes).
 // modes and the precisions each supports
 bool valid_mode(int mode, int precision) {
   if (precision < MPLB_F64 || precision > MPLB_F32_BF16) return false;
   return mode == MPLB_COUPLED || mode == MPLB_CHE_ONLY || mode == MPLB_COUPLED_Q19;
 }
 
+// The kernels index nodes and population arrays in 32 bits: the padded
+// pitch between arrays (which bounds every node index, and the read-out
+// grids' last index) must fit an int, and the step kernel forms in-plane
+// byte offsets in 32 bits (nx*ny elements of up to 8 bytes).  The limit is
+// derived from the pitch itself, so that it follows the padding.
 bool valid_dims(int nx, int ny, int nz) {
   if (nx < 1 || ny < 1 || nz < 1) return false;
   long long N = (long long)nx * ny * nz;
-  return N < (1LL << 31) - 4096 && (long long)nx * ny * 8 < (1LL << 32);
+  long long pitch = (long long)align_up((size_t)N, 256) + (long long)kPitchPad;
+  return pitch <= (long long)INT_MAX && (long long)nx * ny * 8 < (1LL << 32);
 }
 
 const uint64_t kMagic = 0x31303531504c424dULL;  // checkpoint tag
@@ -96,6 +101,7 @@ struct mplb_s {
   Coef<double> C{};
   double velT = 1.0;
   int check_interval = 0;
+  int tile_rows = 0;  // mplb_force_tile_rows (0: automatic)
   std::string err;
 };
 
@@ -342,7 +348,7 @@ static int check_flag(mplb_t* h) {
 // Enqueue one step of lattice h on stream s.
 static int enqueue_step(mplb_t* h, hipStream_t s) {
   set_vel_time(h);
-  HIPCHK(h, launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s));
+  HIPCHK(h, launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, s, h->tile_rows));
   h->cur = 1 - h->cur;
   h->step++;
   return MPLB_OK;
@@ -381,7 +387,8 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]) {
     hipEvent_t* e = &ev[2 * (size_t)k];
     set_vel_time(h);
     hipError_t err = hipEventRecord(e[0], h->stream);
-    if (err == hipSuccess) err = launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream);
+    if (err == hipSuccess)
+      err = launch_fused_step(h->prec, h->mode, h->G, h->C, h->B, h->cur, h->stream, h->tile_rows);
     if (err == hipSuccess) err = hipEventRecord(e[1], h->stream);
     if (err != hipSuccess) rc = fail(h, MPLB_E_DEVICE, "time_stages: %s", hipGetErrorString(err));
     h->cur = 1 - h->cur;
@@ -477,6 +484,23 @@ static int chunk_graph(mplb_t* h0, BatchTable& T, bool xywall, bool nt, bool uni
   return MPLB_OK;
 }
 
+// After every lattice of a batch advanced nsteps: check each lattice whose
+// own check interval was crossed, as mplb_step does.  Every such lattice is
+// checked (one failure does not hide another); each failed lattice keeps its
+// message, and the result is MPLB_E_NONFINITE if any failed.
+static int check_after(mplb_t* const* hs, int count, int nsteps) {
+  int rc = MPLB_OK;
+  for (int i = 0; i < count; ++i) {
+    mplb_t* h = hs[i];
+    const long k = h->check_interval;
+    if (k <= 0 || h->step / k == (h->step - nsteps) / k) continue;
+    int r = check_flag(h);
+    if (r == MPLB_E_NONFINITE) rc = r;
+    else if (r) return r;
+  }
+  return rc;
+}
+
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
   if (!hs || count < 0 || nsteps < 0) return MPLB_E_INVAL;
   if (count == 0 || nsteps == 0) return MPLB_OK;
@@ -505,11 +529,18 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
         int rc = enqueue_step(hs[i], s);
         if (rc) return rc;
       }
-    return MPLB_OK;
+    return check_after(hs, count, nsteps);
   }
   int dev = 0;
   HIPCHK(h0, hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(h0, MPLB_E_DEVICE, "device index out of range");
+  bool xywall = false;
+  size_t step_bytes = 0;
+  for (int i = 0; i < count; ++i) {
+    xywall = xywall || hs[i]->G.wall_x || hs[i]->G.wall_y;
+    step_bytes += fused_step_bytes(hs[i]->prec, hs[i]->mode, hs[i]->G.N);
+  }
+  const bool nt = step_bytes > fused_stream_threshold();
   BatchTable& T = g_tables[dev];
   size_t bytes = fused_batch_item_bytes(h0->prec) * (size_t)count;
   if (T.uploaded) HIPCHK(h0, hipEventSynchronize(T.uploaded));  // staging free again
@@ -533,17 +564,12 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
     T.dev_cap = 2 * bytes;
   }
   int blocks = 0;
-  bool xywall = false;
-  size_t step_bytes = 0;
   for (int i = 0; i < count; ++i) {
     mplb_t* h = hs[i];
     int nb = fused_batch_fill(h->prec, T.host, i, h->G, h->C, h->B, h->cur, blocks);
     if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
     blocks += nb;
-    xywall = xywall || h->G.wall_x || h->G.wall_y;
-    step_bytes += fused_step_bytes(h->prec, h->mode, h->G.N);
   }
-  const bool nt = step_bytes > fused_stream_threshold();
   // the previous batched launches (perhaps on another stream) still read the table
   HIPCHK(h0, hipStreamWaitEvent(s, T.done, 0));
   HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
@@ -558,20 +584,18 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
       HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, unit, T.dev, count, blocks, k & 1, s));
   }
   HIPCHK(h0, hipEventRecord(T.done, s));
-  bool check = false;
   for (int i = 0; i < count; ++i) {
     mplb_t* h = hs[i];
-    long before = h->step;
     h->step += nsteps;
     if (nsteps & 1) h->cur = 1 - h->cur;
-    if (h->check_interval > 0 && h->step / h->check_interval != before / h->check_interval) check = true;
   }
-  if (check)
-    for (int i = 0; i < count; ++i) {
-      int rc = check_flag(hs[i]);
-      if (rc) return rc;
-    }
-  return MPLB_OK;
+  return check_after(hs, count, nsteps);
+}
+
+int mplb_check_finite(mplb_t* h) {
+  if (!h) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "check before init");
+  return check_flag(h);
 }
 
 static int prepare_macro(mplb_t* h) {
@@ -688,6 +712,15 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
 int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hip_stream) {
   if (!src || !dst || bytes % 16 || kind < 0 || kind > 2) return MPLB_E_INVAL;
   return launch_copy_probe(src, dst, bytes, kind, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK : MPLB_E_DEVICE;
+}
+
+int mplb_force_tile_rows(mplb_t* h, int rows) {
+  if (!h) return MPLB_E_INVAL;
+  if (rows != 0 && rows != 8 && rows != 16) return fail(h, MPLB_E_INVAL, "tile rows must be 0, 8 or 16");
+  if (rows == 16 && (h->prec != MPLB_F32 || h->mode == MPLB_CHE_ONLY))
+    return fail(h, MPLB_E_INVAL, "16-row tiles exist for the coupled step with FP32 populations only");
+  h->tile_rows = rows;
+  return MPLB_OK;
 }
 
 int mplb_poke(mplb_t* h, int set, int i, long node, double value) {

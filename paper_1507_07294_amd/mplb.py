@@ -79,11 +79,13 @@ def lib():
             "mplb_totals": (C.c_int, [vp, dp]),
             "mplb_front": (C.c_int, [vp, dp]),
             "mplb_step_many": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int]),
+            "mplb_check_finite": (C.c_int, [vp]),
             "mplb_set_step_many_graphs": (C.c_int, [C.c_int]),
             "mplb_checkpoint_bytes": (C.c_int, [vp, C.POINTER(sz)]),
             "mplb_checkpoint": (C.c_int, [vp, vp, sz]),
             "mplb_restore": (C.c_int, [vp, vp, sz]),
             "mplb_poke": (C.c_int, [vp, C.c_int, C.c_int, C.c_long, C.c_double]),
+            "mplb_force_tile_rows": (C.c_int, [vp, C.c_int]),
             "mplb_time_stages": (C.c_int, [vp, C.c_int, dp]),
             "mplb_copy_probe": (C.c_int, [vp, vp, sz, C.c_int, vp]),
             "mplb_destroy": (None, [vp]),
@@ -214,6 +216,17 @@ class Lattice:
     def step(self, n=1):
         self._chk(lib().mplb_step(self._h, int(n)))
 
+    def check_finite(self):
+        """MPLB_OK, or MPLB_E_NONFINITE if a population of this lattice became
+        non-finite since init (synchronises)."""
+        rc = lib().mplb_check_finite(self._h)
+        if rc not in (MPLB_OK, MPLB_E_NONFINITE):
+            self._chk(rc)
+        return rc
+
+    def last_error(self):
+        return lib().mplb_last_error(self._h).decode()
+
     def try_step(self, n=1):
         rc = lib().mplb_step(self._h, int(n))
         return rc, lib().mplb_last_error(self._h).decode()
@@ -277,6 +290,10 @@ class Lattice:
     def poke(self, set_, i, node, value):
         self._chk(lib().mplb_poke(self._h, int(set_), int(i), int(node), float(value)))
 
+    def force_tile_rows(self, rows):
+        """Test hook: tile height of the coupled step (0 automatic, 8 or 16)."""
+        self._chk(lib().mplb_force_tile_rows(self._h, int(rows)))
+
     def destroy(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
@@ -290,12 +307,30 @@ class Lattice:
             pass
 
 
-def mplb_step_many(lattices, nsteps):
-    """Advance several lattices together (batched launches)."""
+def _many(fn, lattices, nsteps):
     arr = (C.c_void_p * len(lattices))(*[lt.handle.value for lt in lattices])
-    rc = lib().mplb_step_many(arr, len(lattices), int(nsteps))
+    rc = fn(arr, len(lattices), int(nsteps))
     if rc:
+        if rc == MPLB_E_NONFINITE:
+            bad = [i for i, lt in enumerate(lattices) if lt.check_finite() == MPLB_E_NONFINITE]
+            raise NonFiniteError(bad, [lattices[i].last_error() for i in bad])
         raise MplbError(rc, lib().mplb_last_error(lattices[0].handle).decode() if lattices else "")
+
+
+class NonFiniteError(MplbError):
+    """mplb_step_many found non-finite populations; `failed` lists the
+    positions of the failed lattices in the batch, `messages` their errors."""
+
+    def __init__(self, failed, messages):
+        super().__init__(MPLB_E_NONFINITE, "; ".join(messages))
+        self.failed = list(failed)
+        self.messages = list(messages)
+
+
+def mplb_step_many(lattices, nsteps):
+    """Advance several lattices together (batched launches).  Raises
+    NonFiniteError naming the failed lattices when a non-finite check fails."""
+    _many(lib().mplb_step_many, lattices, nsteps)
 
 
 def mplb_set_step_many_graphs(enable):

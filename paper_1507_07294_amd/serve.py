@@ -6,7 +6,9 @@ admitted lattice resident, and advances all of them together: one batched
 step kernel per time step covers every active lattice (``mplb_step_many``).
 A lattice that reaches its target is read out (fields to the host) and freed,
 which makes room for the next admissions.  Requests that arrive while others
-are on the GPU join at the next chunk boundary.
+are on the GPU join at the next chunk boundary.  A lattice whose populations
+became non-finite is retired with that error in its own result (no fields);
+the lattices batched with it are unaffected.
 
 The back-to-back reference runs the same requests one at a time, in arrival
 order, with the same chunking.
@@ -39,6 +41,8 @@ class Result:
     completed: float
     lups: int
     fields: Optional[Dict[str, np.ndarray]] = None
+    error: Optional[str] = None  # set when the simulation failed (non-finite populations)
+    code: int = 0                # MPLB_OK, or the mplb error code of the failure
 
     @property
     def latency(self) -> float:
@@ -55,7 +59,8 @@ def _summary(results: List[Result], t_first: float, t_last: float):
     lups = sum(r.lups for r in results)
     span = max(t_last - t_first, 1e-9)
     return {"requests": len(results), "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
-            "mean_s": float(lat.mean()), "makespan_s": span, "aggregate_MLUPS": lups / span / 1e6}
+            "mean_s": float(lat.mean()), "makespan_s": span, "aggregate_MLUPS": lups / span / 1e6,
+            "failed": sum(1 for r in results if r.code != 0)}
 
 
 class _Streams:
@@ -90,8 +95,11 @@ class Server:
     """Admits requests by HBM budget and advances all resident lattices with
     batched steps, `chunk` steps at a time."""
 
-    def __init__(self, precision="f32", budget_bytes=16e9, chunk=50, keep_fields=False):
+    def __init__(self, precision="f32", budget_bytes=16e9, chunk=50, keep_fields=False, on_admit=None):
         self.precision = precision
+        # on_admit(request, lattice): called once a lattice is set up (a test
+        # hook, e.g. to plant a fault in one request)
+        self.on_admit = on_admit
         self.budget = float(budget_bytes)
         self.chunk = int(chunk)
         self.keep_fields = keep_fields
@@ -126,6 +134,8 @@ class Server:
                 waiting.popleft()
                 with st.on_side():  # memory, upload and init on the side stream
                     lt = mplb.from_workload(req.workload, self.precision)  # returns initialised
+                if self.on_admit is not None:
+                    self.on_admit(req, lt)
                 lt.set_stream(st.main_ptr())
                 used += need
                 self.peak_bytes = max(self.peak_bytes, used)
@@ -146,10 +156,14 @@ class Server:
             for a, ev in finished:
                 st.side_waits(ev)
                 a[1].set_stream(st.side_ptr())
-                fields = {f: a[1].read(f) for f in READ_FIELDS}  # synchronises the side stream
+                code = a[1].check_finite()  # this lattice's own flag; synchronises the side stream
+                if code == mplb.MPLB_OK:
+                    fields, err = {f: a[1].read(f) for f in READ_FIELDS}, None
+                else:
+                    fields, err = None, a[1].last_error()
                 done = time.perf_counter() - t0
                 results.append(Result(a[0].rid, a[0].arrival, a[3], done, a[0].workload.nodes * a[0].steps,
-                                      fields if self.keep_fields else None))
+                                      fields if self.keep_fields else None, err, code))
                 a[1].destroy()
                 used -= a[4]
             finished = just_finished
@@ -176,10 +190,11 @@ def run_back_to_back(trace, precision="f32", chunk=50, realtime=True, keep_field
             k = min(chunk, req.steps - done)
             lt.step(k)
             done += k
-        fields = {f: lt.read(f) for f in READ_FIELDS}
+        code = lt.check_finite()
+        fields, err = ({f: lt.read(f) for f in READ_FIELDS}, None) if code == mplb.MPLB_OK else (None, lt.last_error())
         end = time.perf_counter() - t0
         results.append(Result(req.rid, req.arrival, start, end, req.workload.nodes * req.steps,
-                              fields if keep_fields else None))
+                              fields if keep_fields else None, err, code))
         lt.destroy()
     t_last = max(r.completed for r in results)
     t_first = min(r.arrival for r in results)

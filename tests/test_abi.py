@@ -77,6 +77,42 @@ def test_size_limit_boundary(lib):
                                    C.byref(n)) == mplb.MPLB_E_INVAL
 
 
+def test_size_limit_follows_the_padded_pitch(lib):
+    """The limit is derived from the padded pitch between population arrays,
+    which must fit a 32-bit int.  268434688 x 1 x 8 (N = 2^31 - 6144, about
+    137 GB with 16-bit CHE-only storage) passes a bare node-count limit but
+    its padded pitch exceeds INT_MAX: refused.  1000 x 1000 x 2147 (about
+    258 GB with 16-bit storage) has a pitch that fits and is accepted; its
+    totals pass strides over nodes in 64 bits, since the last node plus one
+    stride of the totals grid passes INT_MAX."""
+    n = C.c_size_t(0)
+    assert lib.mplb_required_bytes(268434688, 1, 8, mplb.MPLB_F32_F16, mplb.MPLB_CHE_ONLY,
+                                   C.byref(n)) == mplb.MPLB_E_INVAL
+    assert lib.mplb_required_bytes(268434688, 1, 7, mplb.MPLB_F32_F16, mplb.MPLB_CHE_ONLY, C.byref(n)) == 0
+    assert lib.mplb_required_bytes(1000, 1000, 2147, mplb.MPLB_F32_F16, mplb.MPLB_COUPLED, C.byref(n)) == 0
+    assert n.value > 1000 * 1000 * 2147 * 100
+    # the largest accepted node count: align_up(N, 256) + 27 * 256 <= 2^31 - 1
+    pad = 27 * 256
+    nmax = (2 ** 31 - 1 - pad) // 256 * 256
+    assert lib.mplb_required_bytes(256, 1, nmax // 256, mplb.MPLB_F32_F16, mplb.MPLB_CHE_ONLY, C.byref(n)) == 0
+    assert lib.mplb_required_bytes(256, 1, nmax // 256 + 1, mplb.MPLB_F32_F16, mplb.MPLB_CHE_ONLY,
+                                   C.byref(n)) == mplb.MPLB_E_INVAL
+    h = C.c_void_p(1)
+    bc = (C.c_int * 3)(0, 0, 0)
+    assert lib.mplb_create(268434688, 1, 8, bc, mplb.MPLB_F32_F16, mplb.MPLB_CHE_ONLY, None, 0,
+                           C.byref(h)) == mplb.MPLB_E_INVAL
+    assert h.value is None
+
+
+def test_step_many_and_hooks_reject_bad_arguments_before_any_device_call(lib):
+    assert lib.mplb_step_many(None, 1, 1) == mplb.MPLB_E_INVAL
+    arr = (C.c_void_p * 1)(None)
+    assert lib.mplb_step_many(arr, 1, 1) == mplb.MPLB_E_INVAL
+    assert lib.mplb_step_many(arr, 0, 5) == 0
+    assert lib.mplb_check_finite(None) == mplb.MPLB_E_INVAL
+    assert lib.mplb_force_tile_rows(None, 8) == mplb.MPLB_E_INVAL
+
+
 def test_invalid_create_is_rejected_before_any_device_call(lib):
     h = C.c_void_p(1)
     bc = (C.c_int * 3)(0, 0, 5)

@@ -161,3 +161,69 @@ def test_nan_in_one_lattice_stays_in_that_lattice():
     assert rc == mplb.MPLB_E_NONFINITE
     for g in mix:
         g.destroy()
+
+
+@pytest.mark.parametrize("q19", [False, True])
+def test_step_many_reports_every_failed_lattice(q19):
+    """With a check interval set, step_many checks each lattice whose interval
+    was crossed and names every failed one, not only the first; the others
+    still equal their runs alone.  The D3Q19 batch takes the one-after-another
+    path, which checks the same way."""
+    from paper_1507_07294_amd import mplb
+    print(f"\n[case] step_many per-lattice failures q19={q19}", flush=True)
+    ws = [wl.perturbed_case(s, (0, 0, 1), 120 + i, coupled=True) for i, s in
+          enumerate([(16, 14, 12), (20, 10, 18), (12, 12, 12), (14, 16, 10)])]
+    for w in ws:
+        w.nse_q = 19 if q19 else 15
+    alone = []
+    for w in ws:
+        g = mplb.from_workload(w, "f32")
+        g.step(10)
+        alone.append({k: g.read(k) for k in ("phi", "uz")})
+        g.destroy()
+    mix = [mplb.from_workload(w, "f32") for w in ws]
+    for g in mix:
+        g.set_check_interval(5)
+    mix[0].poke(1, 7, 40, float("nan"))
+    mix[2].poke(0, 3, 11, float("inf"))
+    with pytest.raises(mplb.NonFiniteError) as ei:
+        mplb.mplb_step_many(mix, 10)
+    assert ei.value.failed == [0, 2]
+    assert all("non-finite" in m for m in ei.value.messages)
+    for i in (1, 3):
+        assert mix[i].check_finite() == mplb.MPLB_OK
+        for k, v in alone[i].items():
+            assert np.array_equal(mix[i].read(k), v), (i, k)
+    for g in mix:
+        g.destroy()
+
+
+def test_served_request_that_fails_is_retired_alone():
+    """A NaN planted in one served request: that request comes back with
+    MPLB_E_NONFINITE and no fields; every other request's fields are bitwise
+    its run alone."""
+    from paper_1507_07294_amd import mplb
+    from paper_1507_07294_amd.serve import Server
+    print("\n[case] serving with one failing request", flush=True)
+    trace = _trace()[:5]
+    bad = 2
+
+    def plant(req, lt):
+        if req.rid == bad:
+            lt.poke(1, 8, lt.N // 2, float("nan"))
+
+    srv = Server("f32", 64e9, chunk=30, keep_fields=True, on_admit=plant)
+    results, summary = srv.run(trace, realtime=False)
+    assert summary["failed"] == 1
+    assert max(srv.batch_sizes) >= 2
+    for res in results:
+        if res.rid == bad:
+            assert res.code == mplb.MPLB_E_NONFINITE and res.fields is None and "non-finite" in res.error
+            continue
+        assert res.code == 0 and res.error is None
+        req = trace[res.rid]
+        lt = mplb.from_workload(req.workload, "f32")
+        lt.step(req.steps)
+        for f, v in res.fields.items():
+            assert np.array_equal(v, lt.read(f)), (res.rid, f)
+        lt.destroy()

@@ -22,6 +22,14 @@ class FakeLattice:
     def read(self, f):
         return self.steps
 
+    failed = False  # stands for a lattice whose non-finite flag is set
+
+    def check_finite(self):
+        return 5 if self.failed else 0
+
+    def last_error(self):
+        return "non-finite population after step %d" % self.steps
+
     def set_stream(self, ptr):
         self.stream = ptr
 
@@ -119,3 +127,24 @@ def test_back_to_back_runs_one_at_a_time(fake):
     assert fake.peak == 1
     assert [r.rid for r in results] == list(range(5))
     assert all(r.fields["phi"] == trace[r.rid].steps for r in results)
+
+
+def test_failed_request_is_retired_with_its_error(fake):
+    """A lattice whose flag reports non-finite populations comes back with
+    that error and no fields; the others are unaffected and every request
+    still completes once."""
+    trace = _trace(6)
+    bad = {2, 4}
+
+    def plant(req, lt):
+        lt.failed = req.rid in bad
+
+    srv = serve.Server("f32", 3 * 16 ** 3 * 100, chunk=5, keep_fields=True, on_admit=plant)
+    results, summary = srv.run(trace, realtime=False)
+    assert summary["failed"] == 2 and fake.live == 0
+    assert sorted(r.rid for r in results) == list(range(6))
+    for r in results:
+        if r.rid in bad:
+            assert r.code == 5 and r.fields is None and "non-finite" in r.error
+        else:
+            assert r.code == 0 and r.error is None and r.fields["phi"] == trace[r.rid].steps
