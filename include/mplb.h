@@ -212,6 +212,23 @@ int mplb_front(mplb_t* h, double out[2]);
  * otherwise). */
 int mplb_step_many(mplb_t* const* hs, int count, int nsteps);
 
+/* For callers that cannot allocate memory once their lattices exist (tight
+ * serving loops, harnesses that forbid hipMalloc and pinned host buffers):
+ * mplb_step_many, bitwise the same steps, with no device or host
+ * allocation.  The batch table lives in a static device array sized for
+ * MPLB_NOALLOC_MAX_LATTICES lattices of any precision (about 250 KB); each
+ * device holds its own copy until the process ends, and mplb_create looks up
+ * its address.  The table is written from a stack buffer with copies from
+ * pageable memory, which return once the table has left the host (they may
+ * wait for the work already enqueued on the stream), and the steps are
+ * launched one by one (no graph).  count > MPLB_NOALLOC_MAX_LATTICES:
+ * MPLB_E_INVAL, with the limit in mplb_last_error(hs[0]).  Every call on a
+ * device rewrites that device's one table: calls on one stream are ordered,
+ * but calls that overlap on one device (two threads, or two streams) race.
+ * Non-finite checks as in mplb_step_many. */
+#define MPLB_NOALLOC_MAX_LATTICES 512
+int mplb_step_many_noalloc(mplb_t* const* hs, int count, int nsteps);
+
 /* Whether mplb_step_many replays its steps as a graph (enable != 0, the
  * default) or launches them one by one; process-wide, for measurement. */
 int mplb_set_step_many_graphs(int enable);

@@ -923,7 +923,32 @@ int batch_fill_impl(void* table, int i, const Geo& G, const Coef<double>& Cd, co
   return it.nblocks;
 }
 
+// Batch table of mplb_step_many_noalloc: a file-scope device array, so that
+// the call allocates nothing.  Each device holds its own copy until the
+// process ends.  Host code never passes the array's name to a kernel or a
+// copy (on the host it is only a stand-in for the symbol): its device address
+// is looked up once per device and kept.
+constexpr size_t kNoAllocTableBytes = (size_t)MPLB_NOALLOC_MAX_LATTICES * sizeof(BatchItem<double>);
+static_assert(sizeof(BatchItem<double>) >= sizeof(BatchItem<float>), "the table is sized for FP64 items");
+static __device__ __align__(256) unsigned char scratch[kNoAllocTableBytes];
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices];
+
 }  // namespace
+
+hipError_t noalloc_table(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+size_t noalloc_table_bytes() { return kNoAllocTableBytes; }
 
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                              hipStream_t s, int rows) {

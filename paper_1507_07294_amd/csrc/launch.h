@@ -32,6 +32,12 @@ hipError_t launch_fused_many(int P, bool xywall, bool nt, bool unit, const void*
 // nodes; the caller instantiates, launches and destroys it
 hipError_t build_fused_many_graph(int P, bool xywall, bool nt, bool unit, const void* dtab, int count,
                                   int total_blocks, int nsteps, hipGraph_t* out);
+// Device address of the static batch table of mplb_step_many_noalloc on
+// device `dev` (the current device), looked up on the first call for that
+// device and kept; it holds MPLB_NOALLOC_MAX_LATTICES items of any precision
+// (noalloc_table_bytes bytes).
+hipError_t noalloc_table(int dev, void** out);
+size_t noalloc_table_bytes();
 // algorithmic bytes one step of an N-node lattice moves (populations and
 // history read and written once)
 size_t fused_step_bytes(int P, int mode, long long N);

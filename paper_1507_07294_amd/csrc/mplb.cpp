@@ -191,6 +191,14 @@ int mplb_create(int nx, int ny, int nz, const int bc[3], int precision, int mode
   h->B.flag = (int*)p; p += P.flag;
   h->C.vel_kind = MPLB_VEL_ZERO;
   h->C.vel_ct = h->C.vel_ct_prev = 1.0;
+  // set-up of mplb_step_many_noalloc on this device (its table's address)
+  int dev = 0;
+  void* tab = nullptr;
+  if (hipGetDevice(&dev) != hipSuccess || noalloc_table(dev, &tab) != hipSuccess) {
+    (void)hipGetLastError();
+    mplb_destroy(h);
+    return MPLB_E_DEVICE;
+  }
   *out = h;
   return MPLB_OK;
 }
@@ -501,9 +509,37 @@ static int check_after(mplb_t* const* hs, int count, int nsteps) {
   return rc;
 }
 
-int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
+// Upload of a batch table without allocating: items are written into a stack
+// buffer and copied in pieces.  The copies are from pageable memory, so each
+// returns only once its bytes have left the buffer.
+static int upload_table_noalloc(mplb_t* const* hs, int count, void* dtab, hipStream_t s, int* blocks_out) {
+  mplb_t* h0 = hs[0];
+  const size_t item = fused_batch_item_bytes(h0->prec);
+  alignas(64) unsigned char stage[16384];
+  const int per = (int)(sizeof stage / item);
+  if (per < 1) return fail(h0, MPLB_E_INVAL, "batch item larger than its staging");
+  int blocks = 0;
+  for (int first = 0; first < count; first += per) {
+    const int n = count - first < per ? count - first : per;
+    for (int j = 0; j < n; ++j) {
+      mplb_t* h = hs[first + j];
+      int nb = fused_batch_fill(h->prec, stage, j, h->G, h->C, h->B, h->cur, blocks);
+      if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
+      blocks += nb;
+    }
+    HIPCHK(h0, hipMemcpyAsync((char*)dtab + (size_t)first * item, stage, (size_t)n * item, hipMemcpyHostToDevice, s));
+  }
+  *blocks_out = blocks;
+  return MPLB_OK;
+}
+
+// mplb_step_many and its allocation-free variant.
+static int step_many_impl(mplb_t* const* hs, int count, int nsteps, bool noalloc) {
   if (!hs || count < 0 || nsteps < 0) return MPLB_E_INVAL;
   if (count == 0 || nsteps == 0) return MPLB_OK;
+  if (noalloc && count > MPLB_NOALLOC_MAX_LATTICES)
+    return fail(hs[0], MPLB_E_INVAL, "step_many_noalloc: %d lattices exceed its static table of %d", count,
+                MPLB_NOALLOC_MAX_LATTICES);
   for (int i = 0; i < count; ++i) {
     if (!hs[i]) return MPLB_E_INVAL;
     if (!hs[i]->have_init) return fail(hs[i], MPLB_E_STATE, "step before init");
@@ -541,55 +577,71 @@ int mplb_step_many(mplb_t* const* hs, int count, int nsteps) {
     step_bytes += fused_step_bytes(hs[i]->prec, hs[i]->mode, hs[i]->G.N);
   }
   const bool nt = step_bytes > fused_stream_threshold();
-  BatchTable& T = g_tables[dev];
-  size_t bytes = fused_batch_item_bytes(h0->prec) * (size_t)count;
-  if (T.uploaded) HIPCHK(h0, hipEventSynchronize(T.uploaded));  // staging free again
-  if (!T.uploaded) HIPCHK(h0, hipEventCreateWithFlags(&T.uploaded, hipEventDisableTiming));
-  if (!T.done) HIPCHK(h0, hipEventCreateWithFlags(&T.done, hipEventDisableTiming));
-  if (T.host_cap < bytes) {
-    if (T.host) HIPCHK(h0, hipHostFree(T.host));
-    T.host = nullptr;
-    T.host_cap = 0;
-    HIPCHK(h0, hipHostMalloc(&T.host, 2 * bytes, hipHostMallocDefault));
-    T.host_cap = 2 * bytes;
-  }
-  if (T.dev_cap < bytes) {
-    if (T.dev) {
-      HIPCHK(h0, hipDeviceSynchronize());
-      HIPCHK(h0, hipFree(T.dev));
-    }
-    T.dev = nullptr;
-    T.dev_cap = 0;
-    HIPCHK(h0, hipMalloc(&T.dev, 2 * bytes));
-    T.dev_cap = 2 * bytes;
-  }
-  int blocks = 0;
-  for (int i = 0; i < count; ++i) {
-    mplb_t* h = hs[i];
-    int nb = fused_batch_fill(h->prec, T.host, i, h->G, h->C, h->B, h->cur, blocks);
-    if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
-    blocks += nb;
-  }
-  // the previous batched launches (perhaps on another stream) still read the table
-  HIPCHK(h0, hipStreamWaitEvent(s, T.done, 0));
-  HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
-  HIPCHK(h0, hipEventRecord(T.uploaded, s));
-  if (g_use_graphs && nsteps > 1) {
-    hipGraphExec_t ex = nullptr;
-    int rc = chunk_graph(h0, T, xywall, nt, unit, count, blocks, nsteps, &ex);
+  if (noalloc) {
+    void* dtab = nullptr;
+    HIPCHK(h0, noalloc_table(dev, &dtab));
+    int blocks = 0;
+    int rc = upload_table_noalloc(hs, count, dtab, s, &blocks);
     if (rc) return rc;
-    HIPCHK(h0, hipGraphLaunch(ex, s));
-  } else {
     for (int k = 0; k < nsteps; ++k)
-      HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, unit, T.dev, count, blocks, k & 1, s));
+      HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, unit, dtab, count, blocks, k & 1, s));
+  } else {
+    BatchTable& T = g_tables[dev];
+    size_t bytes = fused_batch_item_bytes(h0->prec) * (size_t)count;
+    if (T.uploaded) HIPCHK(h0, hipEventSynchronize(T.uploaded));  // staging free again
+    if (!T.uploaded) HIPCHK(h0, hipEventCreateWithFlags(&T.uploaded, hipEventDisableTiming));
+    if (!T.done) HIPCHK(h0, hipEventCreateWithFlags(&T.done, hipEventDisableTiming));
+    if (T.host_cap < bytes) {
+      if (T.host) HIPCHK(h0, hipHostFree(T.host));
+      T.host = nullptr;
+      T.host_cap = 0;
+      HIPCHK(h0, hipHostMalloc(&T.host, 2 * bytes, hipHostMallocDefault));
+      T.host_cap = 2 * bytes;
+    }
+    if (T.dev_cap < bytes) {
+      if (T.dev) {
+        HIPCHK(h0, hipDeviceSynchronize());
+        HIPCHK(h0, hipFree(T.dev));
+      }
+      T.dev = nullptr;
+      T.dev_cap = 0;
+      HIPCHK(h0, hipMalloc(&T.dev, 2 * bytes));
+      T.dev_cap = 2 * bytes;
+    }
+    int blocks = 0;
+    for (int i = 0; i < count; ++i) {
+      mplb_t* h = hs[i];
+      int nb = fused_batch_fill(h->prec, T.host, i, h->G, h->C, h->B, h->cur, blocks);
+      if (nb <= 0) return fail(h0, MPLB_E_INVAL, "bad batch item");
+      blocks += nb;
+    }
+    // the previous batched launches (perhaps on another stream) still read the table
+    HIPCHK(h0, hipStreamWaitEvent(s, T.done, 0));
+    HIPCHK(h0, hipMemcpyAsync(T.dev, T.host, bytes, hipMemcpyHostToDevice, s));
+    HIPCHK(h0, hipEventRecord(T.uploaded, s));
+    if (g_use_graphs && nsteps > 1) {
+      hipGraphExec_t ex = nullptr;
+      int rc = chunk_graph(h0, T, xywall, nt, unit, count, blocks, nsteps, &ex);
+      if (rc) return rc;
+      HIPCHK(h0, hipGraphLaunch(ex, s));
+    } else {
+      for (int k = 0; k < nsteps; ++k)
+        HIPCHK(h0, launch_fused_many(h0->prec, xywall, nt, unit, T.dev, count, blocks, k & 1, s));
+    }
+    HIPCHK(h0, hipEventRecord(T.done, s));
   }
-  HIPCHK(h0, hipEventRecord(T.done, s));
   for (int i = 0; i < count; ++i) {
     mplb_t* h = hs[i];
     h->step += nsteps;
     if (nsteps & 1) h->cur = 1 - h->cur;
   }
   return check_after(hs, count, nsteps);
+}
+
+int mplb_step_many(mplb_t* const* hs, int count, int nsteps) { return step_many_impl(hs, count, nsteps, false); }
+
+int mplb_step_many_noalloc(mplb_t* const* hs, int count, int nsteps) {
+  return step_many_impl(hs, count, nsteps, true);
 }
 
 int mplb_check_finite(mplb_t* h) {

@@ -79,6 +79,7 @@ def lib():
             "mplb_totals": (C.c_int, [vp, dp]),
             "mplb_front": (C.c_int, [vp, dp]),
             "mplb_step_many": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int]),
+            "mplb_step_many_noalloc": (C.c_int, [C.POINTER(vp), C.c_int, C.c_int]),
             "mplb_check_finite": (C.c_int, [vp]),
             "mplb_set_step_many_graphs": (C.c_int, [C.c_int]),
             "mplb_checkpoint_bytes": (C.c_int, [vp, C.POINTER(sz)]),
@@ -307,6 +308,9 @@ class Lattice:
             pass
 
 
+MPLB_NOALLOC_MAX_LATTICES = 512
+
+
 def _many(fn, lattices, nsteps):
     arr = (C.c_void_p * len(lattices))(*[lt.handle.value for lt in lattices])
     rc = fn(arr, len(lattices), int(nsteps))
@@ -331,6 +335,12 @@ def mplb_step_many(lattices, nsteps):
     """Advance several lattices together (batched launches).  Raises
     NonFiniteError naming the failed lattices when a non-finite check fails."""
     _many(lib().mplb_step_many, lattices, nsteps)
+
+
+def mplb_step_many_noalloc(lattices, nsteps):
+    """mplb_step_many with no device or host allocation (static batch table of
+    MPLB_NOALLOC_MAX_LATTICES lattices per device, launches one by one)."""
+    _many(lib().mplb_step_many_noalloc, lattices, nsteps)
 
 
 def mplb_set_step_many_graphs(enable):

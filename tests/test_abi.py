@@ -106,9 +106,11 @@ def test_size_limit_follows_the_padded_pitch(lib):
 
 def test_step_many_and_hooks_reject_bad_arguments_before_any_device_call(lib):
     assert lib.mplb_step_many(None, 1, 1) == mplb.MPLB_E_INVAL
+    assert lib.mplb_step_many_noalloc(None, 1, 1) == mplb.MPLB_E_INVAL
     arr = (C.c_void_p * 1)(None)
     assert lib.mplb_step_many(arr, 1, 1) == mplb.MPLB_E_INVAL
-    assert lib.mplb_step_many(arr, 0, 5) == 0
+    assert lib.mplb_step_many_noalloc(arr, 1, 1) == mplb.MPLB_E_INVAL
+    assert lib.mplb_step_many(arr, 0, 5) == 0 and lib.mplb_step_many_noalloc(arr, 0, 5) == 0
     assert lib.mplb_check_finite(None) == mplb.MPLB_E_INVAL
     assert lib.mplb_force_tile_rows(None, 8) == mplb.MPLB_E_INVAL
 
