@@ -25,14 +25,36 @@ VEL_ZERO, VEL_FIELD, VEL_ZALESAK, VEL_DEFORM = 0, 1, 2, 3
 E_NONFINITE = 5
 
 
-def build(verbose: bool = False) -> str:
-    """Compile orc.c into liborc.so (gcc, FP64, no FMA contraction, OpenMP)."""
-    cmd = ["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-           "-Wall", "-o", LIB_PATH, os.path.join(_HERE, "orc.c"), "-lm"]
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=undefined"]
+
+
+def build(verbose: bool = False, sanitize: bool = False, path: str = None) -> str:
+    """Compile orc.c into liborc.so (gcc, FP64, no FMA contraction, OpenMP).
+    sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build (host
+    code, for checking the oracle itself; load it with the sanitizer runtimes
+    preloaded, see sanitizer_env)."""
+    out = path or LIB_PATH
+    opt = SANITIZE_FLAGS if sanitize else ["-O2"]
+    cmd = ["gcc"] + opt + ["-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                           "-Wall", "-o", out, os.path.join(_HERE, "orc.c"), "-lm"]
     if verbose:
         print(" ".join(cmd))
     subprocess.run(cmd, check=True)
-    return LIB_PATH
+    return out
+
+
+def sanitizer_env(lib_path: str) -> dict:
+    """Environment for a Python process that loads a sanitizer build of the
+    oracle: the runtimes preloaded (Python itself is not instrumented), leak
+    checks off (the interpreter keeps its allocations), any finding fatal."""
+    rt = [subprocess.run(["gcc", "-print-file-name=" + n], capture_output=True, text=True,
+                         check=True).stdout.strip() for n in ("libasan.so", "libubsan.so")]
+    env = dict(os.environ)
+    env.update({"LD_PRELOAD": ":".join(rt), "ORC_LIB_PATH": lib_path,
+                "ASAN_OPTIONS": "detect_leaks=0:abort_on_error=1",
+                "UBSAN_OPTIONS": "halt_on_error=1:print_stacktrace=1"})
+    return env
 
 
 class OrcParams(C.Structure):
