@@ -11,8 +11,16 @@ space, independently of the oracle):
   Pe = 50 read as M = 0.1024, S^f of Eq. 45) the step is linearly unstable once
   the flow speed exceeds about 0.02: G(q) has an eigenvalue above 1 at short
   wavelengths, and the oracle's perturbation grows at exactly that rate,
-  while below that speed every mode is bounded.  This is why the printed
-  Rayleigh-Taylor runs diverge under these readings.
+  while below that speed every mode is bounded;
+* the coupled step (CHE and NSE), linearised from the independent NumPy step
+  of bruteforce.py about a bulk phase under a uniform flow, is unstable at a
+  lower speed still: at the W = 256, Re = 4000 Rayleigh-Taylor parameters a
+  grid-scale mode grows by 1.0048 per step at |u| = 0.01 and already grows at
+  |u| = 0.005.  It needs the density contrast and is damped by viscosity and
+  by the bulk diffusion of the Cahn-Hilliard equation, 8 beta M, which the
+  printed sigma = 1e-4 makes small.  The oracle follows the dominant coupled
+  mode exactly.  This is why the printed Rayleigh-Taylor runs diverge under
+  these readings.
 """
 import numpy as np
 import pytest
@@ -121,3 +129,60 @@ def test_oracle_grows_at_the_predicted_rate():
     want = ev[k] ** 1500 * a[:7]
     assert abs(ev[k]) ** 1500 > 300
     assert np.abs(got - want).max() < 1e-6 * np.abs(want).max()
+
+
+def _rt_bulk(W=256, Re=4000.0, sigma=1e-4, **kw):
+    """Rayleigh-Taylor parameters with rho_ref at the light bulk (phi = -1), so
+    that the uniform bulk is at rest under gravity."""
+    p = wl.rayleigh_taylor(W=W, Re=Re, sigma=sigma).params
+    return p.replace(rho_ref=p.rho_g, **kw)
+
+
+U_RT = 0.01 * np.array([0.3, 0.0, 1.0]) / np.sqrt(1.09)
+
+
+def test_coupled_bulk_is_unstable_at_the_rt_parameters():
+    """Coupled linearisation on a 16^3 box about phi = -1 under |u| = 0.01:
+    unstable at W = 256, Re = 4000 (1.0048 per step, a mode with k_z = pi)
+    and at W = 128, Re = 1024 (1.0033); already at |u| = 0.005 (1.00018).
+    Stable with equal densities, with 16 times the viscosity, with 10 times
+    the mobility or with sigma = 1e-3."""
+    lam, idx, _ = vn.coupled_largest_growth(_rt_bulk(), (16, 16, 16), -1.0, U_RT)
+    assert 1.0045 < lam < 1.0052 and idx[0] == 8, (lam, idx)
+    lam, _, _ = vn.coupled_largest_growth(_rt_bulk(W=128, Re=1024.0), (16, 16, 16), -1.0, U_RT)
+    assert 1.0030 < lam < 1.0036, lam
+    lam, _, _ = vn.coupled_largest_growth(_rt_bulk(), (16, 16, 16), -1.0, 0.5 * U_RT)
+    assert 1.0001 < lam < 1.0003, lam
+    base = _rt_bulk()
+    for p in (base.replace(rho_l=base.rho_g), base.replace(nu=16 * base.nu), base.replace(mobility=10 * base.mobility),
+              _rt_bulk(sigma=1e-3)):
+        lam, _, _ = vn.coupled_largest_growth(p, (16, 16, 16), -1.0, U_RT)
+        assert lam < 1 + 1e-9, lam
+
+
+def test_oracle_follows_the_dominant_coupled_mode():
+    """The oracle's coupled step started on the dominant eigenvector of the
+    linearisation above (W = 256, Re = 4000, |u| = 0.01; all 25 state
+    components of one Fourier mode): after 400 steps the mode's complex
+    amplitude in every f and g is lambda^400 times the initial one, to 1e-6."""
+    p = _rt_bulk()
+    shape = (16, 16, 16)
+    _, idx, G = vn.coupled_largest_growth(p, shape, -1.0, U_RT)
+    ev, V = np.linalg.eig(G[idx])
+    k = int(np.argmax(np.abs(ev)))
+    v = V[:, k] / np.abs(V[:22, k]).max()
+    _, base = vn.coupled_base(p, shape, -1.0, U_RT)
+    kvec = 2 * np.pi * np.fft.fftfreq(16)[[idx[2], idx[1], idx[0]]]
+    z, y, x = np.meshgrid(np.arange(16), np.arange(16), np.arange(16), indexing="ij")
+    ph = np.exp(1j * (kvec[0] * x + kvec[1] * y + kvec[2] * z))
+    eps = 1e-8
+    st = base + eps * np.real(v[:, None, None, None] * ph)
+    o = orc.Oracle(shape, (0, 0, 0), orc.COUPLED, p)
+    o.init(np.full((16, 16, 16), -1.0), np.stack([np.full((16, 16, 16), c) for c in U_RT]))
+    o.set_state(f=st[:7], g=st[7:22], phiu=st[22:])
+    o.step(400)
+    f, g, _ = o.get_state()
+    got = 2.0 * ((np.concatenate([f, g]) - base[:22]) * np.conj(ph)).reshape(22, -1).mean(axis=1) / eps
+    want = ev[k] ** 400 * v[:22]
+    assert abs(ev[k]) ** 400 > 5
+    assert np.abs(got - want).max() < 1e-6 * np.abs(want).max(), np.abs(got - want).max() / np.abs(want).max()

@@ -19,6 +19,9 @@ phi u by the backward difference of Eq. 34.  One step, for one wave vector q:
 
 so the step is an 8 x 8 complex matrix G(q).  The velocity tables, M and the
 weights come from the golden fixtures of the printed equations.
+
+The second part linearises the whole coupled step (both lattices) about a
+uniform bulk state by impulse responses of the NumPy step of bruteforce.py.
 """
 from __future__ import annotations
 
@@ -89,3 +92,49 @@ def largest_growth(shape, u, sigma, D, mobility, s_f, source=True):
         if r > best[0]:
             best = (r, q)
     return best
+
+
+# ---------------------------------------------------------------------------
+# The coupled step (Eqs. 4 and 20 with Eqs. 28-36) linearised about a uniform
+# bulk state, from the independent NumPy step of bruteforce.py.  On a
+# periodic box a uniform state (phi_b, u, p = 0, G = 0 with rho_ref the bulk
+# density) is a fixed point and the step is the same at every node, so its
+# linearisation is diagonal in Fourier space: the response to a unit impulse
+# in state component j at node 0 is, after an FFT over the box, column j of
+# G(k) for every wave vector k at once.  The state of a node is the 7 f, the
+# 15 g and the 3 words of (phi u) of the previous level.
+# ---------------------------------------------------------------------------
+
+def coupled_base(params, shape, phi_b, u):
+    """The uniform state (f, g, (phi u)_prev) of the NumPy step."""
+    nx, ny, nz = shape
+    B = bf.Brute(shape, (0, 0, 0), params, coupled=True)
+    uf = np.stack([np.full((nz, ny, nx), float(v)) for v in u])
+    f, g, pu = B.init(np.full((nz, ny, nx), float(phi_b)), uf)
+    return B, np.concatenate([f, g, pu])
+
+
+def coupled_step_matrices(params, shape, phi_b, u, eps=1e-7):
+    """G(k) of the coupled step on a periodic box, shape (nz, ny, nx, 25, 25),
+    by central differences of impulse responses, and the base state."""
+    nx, ny, nz = shape
+    B, base = coupled_base(params, shape, phi_b, u)
+    D = base.shape[0]
+    G = np.zeros((D, D, nz, ny, nx), dtype=complex)
+    for j in range(D):
+        r = []
+        for s in (1.0, -1.0):
+            st = base.copy()
+            st[j, 0, 0, 0] += s * eps
+            fa, ga, pa = B.step(st[:7], st[7:22], st[22:])
+            r.append(np.concatenate([fa, ga, pa]))
+        G[:, j] = np.fft.fftn((r[0] - r[1]) / (2 * eps), axes=(1, 2, 3))
+    return np.moveaxis(G, (0, 1), (-2, -1)), base
+
+
+def coupled_largest_growth(params, shape, phi_b, u):
+    """(max |lambda| over the box's wave vectors, its (kz, ky, kx) index, G)."""
+    G, _ = coupled_step_matrices(params, shape, phi_b, u)
+    lam = np.abs(np.linalg.eigvals(G.reshape(-1, G.shape[-1], G.shape[-1]))).max(axis=1)
+    idx = np.unravel_index(int(lam.argmax()), G.shape[:3])
+    return float(lam.max()), idx, G
