@@ -42,9 +42,12 @@ def parse():
     ap.add_argument("--no-q19", action="store_true", help="skip the D3Q19 variant of the NSE lattice")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true", help="also run a plain device copy of known size")
-    ap.add_argument("--serving-requests", type=int, default=48,
+    ap.add_argument("--serving-requests", type=int, default=256,
                     help="requests in the serving trace (0: skip the serving leg)")
-    ap.add_argument("--serving-steps", type=int, default=400)
+    ap.add_argument("--serving-steps", type=int, default=2000, help="steps of each droplet request")
+    ap.add_argument("--serving-rt-steps", type=int, default=400,
+                    help="steps of each Rayleigh-Taylor request (the printed parameters leave the physical "
+                         "range near step 1000 on a W = 32 box and fail near 1800)")
     return ap.parse_args()
 
 
@@ -233,18 +236,27 @@ def main():
             torch.cuda.empty_cache()
 
     if not args.no_che:
-        wc = wl.deformation_flow(n=128)
-        print("[bench] deformation_flow 128^3 f32 (CHE only)", file=sys.stderr, flush=True)
-        lt = mplb.from_workload(wc, "f32")
-        steps = args.steps
-        dtc, stc = time_lattice(lt, steps, args.warmup)
-        result["che_only"] = {"workload": "deformation_flow_128^3", "MLUPS": round(wc.nodes * steps / dtc / 1e6, 1),
-                              "ms_per_step": round(dtc / steps * 1e3, 4),
-                              "hbm_frac_step": round(CHE_ALGO_BYTES["f32"] * wc.nodes / (dtc / steps) / 1e9
-                                                     / HBM_PEAK_GBPS, 4)}
-        lt.destroy()
-        del lt
-        torch.cuda.empty_cache()
+        # the interface-tracking step on the 128^3 box of the paper's tests
+        # (its 126 MB stay in the last-level cache) and on 256^3 (1.07 GB
+        # moved per step, bound by HBM)
+        for n, key in ((128, "che_only"), (256, "che_only_256")):
+            wc = wl.deformation_flow(n=n)
+            print(f"[bench] deformation_flow {n}^3 f32 (CHE only)", file=sys.stderr, flush=True)
+            lt = mplb.from_workload(wc, "f32")
+            steps = args.steps
+            dtc, stc = time_lattice(lt, steps, args.warmup)
+            kc = CHE_ALGO_BYTES["f32"] * wc.nodes / (stc[2] * 1e-3) / 1e9
+            result[key] = {"workload": f"deformation_flow_{n}^3", "MLUPS": round(wc.nodes * steps / dtc / 1e6, 1),
+                           "ms_per_step": round(dtc / steps * 1e3, 4),
+                           "algorithmic_bytes_per_lup": CHE_ALGO_BYTES["f32"],
+                           "hbm_frac_step": round(CHE_ALGO_BYTES["f32"] * wc.nodes / (dtc / steps) / 1e9
+                                                  / HBM_PEAK_GBPS, 4),
+                           "k_step_ms": round(stc[2], 4), "k_achieved_GBps": round(kc, 1),
+                           "k_frac": round(kc / HBM_PEAK_GBPS, 4),
+                           "traffic": measured_traffic("k_fused_che", f"deformation_flow_{n}^3", "f32")}
+            lt.destroy()
+            del lt
+            torch.cuda.empty_cache()
 
     if args.copy_probe:
         # bandwidth reference: the library's 16-byte copies (plain, streaming
@@ -272,9 +284,10 @@ def main():
 
     if args.serving_requests > 0:
         from paper_1507_07294_amd import serve
-        print(f"[bench] serving {args.serving_requests} requests x {args.serving_steps} steps",
-              file=sys.stderr, flush=True)
-        trace = wl.serving_trace(n_requests=args.serving_requests, steps=args.serving_steps, mean_gap_s=0.003)
+        print(f"[bench] serving {args.serving_requests} requests x {args.serving_steps} / {args.serving_rt_steps} "
+              "steps", file=sys.stderr, flush=True)
+        trace = wl.serving_trace(n_requests=args.serving_requests, steps=args.serving_steps, mean_gap_s=0.003,
+                                 rt_steps=args.serving_rt_steps)
         srv = serve.Server("f32", 16e9, chunk=50)
         _, mix = srv.run(trace)
         mplb.mplb_set_step_many_graphs(False)  # the same batched loop, steps launched one by one
@@ -289,8 +302,9 @@ def main():
         _, mix16 = srv16.run(trace)
         result["serving"] = {
             "trace": f"{args.serving_requests} requests, Poisson arrivals (mean gap 3 ms, seed 20261202), half "
-                     f"droplets (32^3..128^3) half Rayleigh-Taylor (W = 32..64), {args.serving_steps} steps each, "
-                     "FP32, HBM budget 16 GB",
+                     f"droplets (32^3..128^3, {args.serving_steps} steps each) half Rayleigh-Taylor (W = 32..64, "
+                     f"{args.serving_rt_steps} steps each: the printed parameters leave the physical range near "
+                     "step 1000 at W = 32), FP32, HBM budget 16 GB",
             "batched": {k: round(v, 4) for k, v in mix.items()},
             "batched_without_graphs": {k: round(v, 4) for k, v in mix_nog.items()},
             "back_to_back": {k: round(v, 4) for k, v in b2b.items()},

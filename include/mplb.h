@@ -261,12 +261,13 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hi
  * node n) of the current state with `value`, e.g. to plant a NaN. */
 int mplb_poke(mplb_t* h, int set, int i, long node, double value);
 
-/* Test hook: the tile height of this lattice's coupled step.  0 (default)
- * lets mplb_step choose (16 rows for FP32 populations on a lattice that
- * fills at least 512 such tiles, 8 otherwise); 8 or 16 forces one (16: FP32
- * populations only, else MPLB_E_INVAL).  The tiling changes which work a
- * block does, not the arithmetic of a node, so the fields are bitwise the
- * same; mplb_step_many always uses 8 rows. */
+/* Test hook: the tile height of this lattice's step.  0 (default) lets
+ * mplb_step choose: 16 rows on a lattice that fills at least 512 such tiles
+ * for the coupled step with FP32 populations and for the CHE-only step in
+ * FP32 compute (any storage; there a thread owns two rows), 8 otherwise.  8
+ * or 16 forces one (16 where it exists, else MPLB_E_INVAL).  The tiling
+ * changes which work a block does, not the arithmetic of a node, so the
+ * fields are bitwise the same; mplb_step_many always uses 8 rows. */
 int mplb_force_tile_rows(mplb_t* h, int rows);
 
 void mplb_destroy(mplb_t* h);

@@ -743,6 +743,141 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   plane(z1 - 1, std::false_type{});
 }
 
+// CHE-only with two rows per thread: a block of 64 x 8 threads owns a
+// 64 x 16 tile, thread (tx, ty) the nodes of rows ty and ty + 8.  The ring's
+// halo of one falls from 29 % to 16 % of the tile's own pulls, each wave has
+// twice the loads in flight per plane, and the LDS (a 4-plane phi ring and a
+// 2-plane queue for 1024 nodes, 76 KB in FP32) still lets two blocks share a
+// CU.  Otherwise the march of k_fused_che: at plane z the pulls of plane z+2
+// are issued, plane z is finished while they are in flight, and their phi
+// goes into the ring before the one barrier of the plane.
+template <int P, bool XYWALL, bool NT, int V = 0>
+__global__ void __launch_bounds__(kTX * 8) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
+k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+  using T = typename Prec<P>::T;
+  using L = Lat<P, false>;
+  constexpr int TY = 16, NTH = kTX * 8;
+  constexpr int PX = kTX + 2, PY = TY + 2, NPHI = PX * PY;
+  constexpr int NNODE = kTX * TY;
+  constexpr int NHALO = NPHI - NNODE;
+  static_assert(NHALO <= NTH, "one halo position per thread");
+  __shared__ T sphi[4][NPHI];
+  __shared__ T sfq[2][7 * NNODE];  // the own nodes' pulled f of planes z, z+1
+  const int lb = logical_block(blockIdx.x, gridDim.x);
+  const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
+  const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
+  const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
+  const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
+  const int gx = x0 + tx;
+  const void* fin = B.f[cur];
+  void* fo = B.f[1 - cur];
+  T* hist = (T*)B.phiu;
+  // own nodes (a node outside the lattice maps onto its periodic image or
+  // its mirror at a wall, whose phi the ring needs there)
+  Column oc[2];
+  int oxy[2], olds[2], gy[2];
+  bool own[2];
+  PrescColumn<T> pcol[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    gy[r] = y0 + ty + 8 * r;
+    own[r] = gx < G.nx && gy[r] < G.ny;
+    const int mx = map_axis(gx, G.nx, G.wall_x), my = map_axis(gy[r], G.ny, G.wall_y);
+    oc[r] = make_column<XYWALL>(G, mx, my);
+    oxy[r] = mx + G.nx * my;
+    olds[r] = (ty + 8 * r + 1) * PX + tx + 1;
+    pcol[r].init(G, C, gx, gy[r]);
+  }
+  // one halo position for each of the first NHALO threads
+  const bool hon = threadIdx.x < NHALO;
+  int hpx = 0, hpy = 0;
+  if (hon) halo_pos<PX, PY, 1>(threadIdx.x, hpx, hpy);
+  const int hx = map_axis(x0 - 1 + hpx, G.nx, G.wall_x), hy = map_axis(y0 - 1 + hpy, G.ny, G.wall_y);
+  const Column hc = make_column<XYWALL>(G, hx, hy);
+  const int hxy = hx + G.nx * hy, hlds = hpy * PX + hpx;
+
+  struct Pending {
+    F7Raw<P, false> o[2], h;
+  };
+  auto issue = [&](int zl, Pending& pd) {
+    const int mz = map_axis(zl, G.nz, G.wall_z);
+    const Plane p = make_plane(G, mz);
+    const int zo = mz * G.nx * G.ny;
+    pull_f7_raw<P, false, XYWALL>(G, fin, oc[0], p, zo, oxy[0], pd.o[0]);
+    pull_f7_raw<P, false, XYWALL>(G, fin, oc[1], p, zo, oxy[1], pd.o[1]);
+    if (hon) pull_f7_raw<P, false, XYWALL>(G, fin, hc, p, zo, hxy, pd.h);
+  };
+  auto finish = [&](const Pending& pd, T* s, T* q) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      T f[7];
+      cvt_f7<P, false>(pd.o[r], f);
+      s[olds[r]] = phi_of(f);
+      if (q) {
+#pragma unroll
+        for (int i = 0; i < 7; ++i) q[i * NNODE + threadIdx.x + r * NTH] = f[i];
+      }
+    }
+    if (hon) {
+      T fh[7];
+      cvt_f7<P, false>(pd.h, fh);
+      s[hlds] = phi_of(fh);
+    }
+  };
+  {
+    Pending pd;
+    issue(z0 - 1, pd);
+    finish(pd, sphi[(z0 - 1 + 8) % 4], nullptr);
+    issue(z0, pd);
+    finish(pd, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
+    issue(z0 + 1, pd);
+    finish(pd, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
+  }
+  __syncthreads();
+  auto plane = [&](int z, auto pull) {
+    constexpr bool PULL = decltype(pull)::value;
+    const int zo = z * G.nx * G.ny;
+    // the history loads first: the memory counter retires in order
+    T phip[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) phip[r] = own[r] ? ld_at(hist + zo, oxy[r]) : (T)0;
+    Pending pd;
+    if constexpr (PULL) issue(z + 2, pd);
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      if (!own[r]) continue;
+      T f[7];
+#pragma unroll
+      for (int i = 0; i < 7; ++i) f[i] = sfq[z % 2][i * NNODE + threadIdx.x + r * NTH];
+      const T phi = phi_of(f);
+      const T lap = lap_lds<T, PX>(sphi[(z - 1 + 8) % 4], sphi[(z + 8) % 4], sphi[(z + 1 + 8) % 4], olds[r],
+                                   (V & kVarS7) != 0);
+      const T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
+      T u[3], up[3];
+      pcol[r].at(G, C, (const T*)B.ufield, gx, gy[r], z, zo + oxy[r], u, up);
+      st_at<NT>(hist + zo, oxy[r], phi);  // Eq. 34: only phi of this level is kept
+      T dphiu[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) dphiu[a] = phi * u[a] - phip[r] * up[a];
+      collide_che(C, f, phi, mu, u, dphiu);
+      st_at<NT>(L::f0(fo) + zo, oxy[r], (typename L::S0)f[0]);
+      typename L::S* fa = L::fi(fo, G.pitch);
+#pragma unroll
+      for (int i = 1; i < 7; ++i)
+        st_at<NT>(fa + ((size_t)(i - 1) * G.pitch + zo), oxy[r], (typename L::S)f[i]);
+      if (!all_finite(f, 7)) *B.flag = 1;
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (PULL) {
+      finish(pd, sphi[(z + 2 + 8) % 4], sfq[z % 2]);
+      __syncthreads();
+    }
+  };
+  for (int z = z0; z < z1 - 1; ++z) plane(z, std::true_type{});
+  plane(z1 - 1, std::false_type{});
+}
+
 template <class T>
 Coef<T> cast_coef_f(const Coef<double>& c) {
   Coef<T> o;
@@ -772,12 +907,12 @@ constexpr int coupled_ty() { return P == MPLB_F32 ? 16 : kTY; }
 // Segment length along z: enough blocks for a few rounds over the 256 CUs
 // (four rounds at two 8-row blocks per CU, two at one 16-row block), but long
 // segments where possible (each segment re-reads a few planes).
-Tiling make_tiling(const Geo& G, int TY, int min_lz) {
+Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0) {
   Tiling t;
   t.tiles_x = (G.nx + kTX - 1) / kTX;
   t.tiles_y = (G.ny + TY - 1) / TY;
   int cols = t.tiles_x * t.tiles_y;
-  int target = TY >= 16 ? 512 : 2048;
+  if (target <= 0) target = TY >= 16 ? 512 : 2048;
   int want = (target + cols - 1) / cols;
   int lz = (G.nz + want - 1) / want;
   if (lz < min_lz) lz = min_lz;
@@ -809,6 +944,16 @@ void launch_coupled(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, 
 // and 8-row tiles took 26 % less time per step on the serving trace's boxes.
 constexpr int kMinBlocksTall = 512;
 
+// CHE-only tiling.  Two rows per thread (k_fused_che2, 64 x 16 tiles) with
+// segments sized for 512 blocks, one round of the chip at two blocks per CU
+// (32-plane segments at 256^3), wherever a lattice fills that many; 8-row
+// tiles (k_fused_che) otherwise and for FP64, whose two-row LDS would not let
+// two blocks share a CU.  Measured on 256^3 (FP32): 254 -> 236 us per step
+// (8-row tiles with 32-plane segments: 248; two rows with 8- or 16-plane
+// segments: 245, 238); FP16 storage 219 -> 190 us; 128^3 unchanged (33 us),
+// where two-row tiles would halve the blocks.  Same bits in every variant.
+constexpr int kCheTarget2 = 512, kCheMinLz2 = 8, kCheMinBlocks2 = 512;
+
 template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s, int rows) {
@@ -825,6 +970,14 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
+    if constexpr (sizeof(typename Prec<P>::T) == 4) {
+      Tiling t2 = make_tiling(G, 16, kCheMinLz2, kCheTarget2);
+      if (rows == 16 || (rows == 0 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2)) {
+        hipLaunchKernelGGL((k_fused_che2<P, XYWALL, NT, V & kVarS7>), dim3((unsigned)(t2.tiles_x * t2.tiles_y * t2.nseg)),
+                           dim3(kTX * 8), 0, s, G, C, B, cur, t2);
+        return hipGetLastError();
+      }
+    }
     Tiling tl = make_tiling(G, kTY, 8);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,

@@ -769,8 +769,9 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hi
 int mplb_force_tile_rows(mplb_t* h, int rows) {
   if (!h) return MPLB_E_INVAL;
   if (rows != 0 && rows != 8 && rows != 16) return fail(h, MPLB_E_INVAL, "tile rows must be 0, 8 or 16");
-  if (rows == 16 && (h->prec != MPLB_F32 || h->mode == MPLB_CHE_ONLY))
-    return fail(h, MPLB_E_INVAL, "16-row tiles exist for the coupled step with FP32 populations only");
+  if (rows == 16 && (h->mode == MPLB_CHE_ONLY ? h->prec == MPLB_F64 : h->prec != MPLB_F32))
+    return fail(h, MPLB_E_INVAL,
+                "16-row tiles exist for the coupled step with FP32 populations and the CHE-only step in FP32 compute");
   h->tile_rows = rows;
   return MPLB_OK;
 }

@@ -13,7 +13,7 @@ the lattices batched with it are unaffected.
 The back-to-back reference runs the same requests one at a time, in arrival
 order, with the same chunking.
 
-    python -m paper_1507_07294_amd.serve [--requests 64] [--steps 400] [--budget-gb 16]
+    python -m paper_1507_07294_amd.serve [--requests 256] [--steps 2000] [--rt-steps 400] [--budget-gb 16]
 """
 from __future__ import annotations
 
@@ -203,14 +203,16 @@ def run_back_to_back(trace, precision="f32", chunk=50, realtime=True, keep_field
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--requests", type=int, default=64)
-    ap.add_argument("--steps", type=int, default=400)
+    ap.add_argument("--requests", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=2000, help="steps of each droplet request")
+    ap.add_argument("--rt-steps", type=int, default=400, help="steps of each Rayleigh-Taylor request")
     ap.add_argument("--gap-ms", type=float, default=5.0, help="mean Poisson inter-arrival time")
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--chunk", type=int, default=50)
     ap.add_argument("--precision", default="f32")
     args = ap.parse_args(argv)
-    trace = wl.serving_trace(n_requests=args.requests, steps=args.steps, mean_gap_s=args.gap_ms / 1e3)
+    trace = wl.serving_trace(n_requests=args.requests, steps=args.steps, mean_gap_s=args.gap_ms / 1e3,
+                             rt_steps=args.rt_steps)
     srv = Server(args.precision, args.budget_gb * 1e9, args.chunk)
     _, mix = srv.run(trace)
     _, b2b = run_back_to_back(trace, args.precision, args.chunk)

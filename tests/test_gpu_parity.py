@@ -339,6 +339,60 @@ def test_che_only(kind, precision, tol):
     _compare(w, [1, 7, 40], precision, tol, coupled=False)
 
 
+def _che_velocity(w, kind, rng):
+    if kind == "field":
+        w.velocity = {"kind": "field", "field": wl.smooth_field(w.shape, rng, 0.03, components=3)}
+    elif kind == "zalesak":
+        w.velocity = {"kind": "zalesak", "U": 0.02}
+    else:
+        w.velocity = {"kind": "deformation", "U": 0.02, "T": 0.05}
+    return w
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3), ("bf16", 5e-2)])
+@pytest.mark.parametrize("kind,shape,bc,seed", [("deformation", (70, 37, 29), (0, 0, 0), 31),
+                                                ("field", (65, 17, 40), (1, 1, 1), 32),
+                                                ("zalesak", (130, 20, 24), (0, 1, 0), 33)])
+def test_che_only_two_row_tiles(precision, tol, kind, shape, bc, seed):
+    """The CHE-only kernel with two rows per thread (64 x 16 tiles; forced
+    here, chosen by itself on lattices of at least 512 such tiles) against
+    the oracle after 30 steps, and bitwise against 8-row tiles: ragged tiles
+    in x and y, walls on every axis or on y only."""
+    print(f"\n[case] CHE two-row tiles {kind} {shape} bc={bc} {precision}", flush=True)
+    w = _che_velocity(wl.perturbed_case(shape, bc, seed, coupled=False), kind, np.random.default_rng(seed))
+    o = helpers.oracle_for(w)
+    o.step(30)
+    ref = helpers.fields_of(o, False)
+    out = {}
+    for rows in (8, 16):
+        g = helpers.gpu_for(w, precision)
+        g.force_tile_rows(rows)
+        g.step(30)
+        out[rows] = helpers.fields_of(g, False)
+        g.destroy()
+    for k in out[8]:
+        assert np.array_equal(out[8][k], out[16][k]), k
+    errs = helpers.rel_errors(out[16], ref)
+    print("  " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    for k, e in errs.items():
+        assert e <= (tol[k] if isinstance(tol, dict) else tol), (k, e)
+
+
+def test_che_only_256_full_field():
+    """The 256^3 interface-tracking box in the launch configuration the
+    benchmark times (two rows per thread, 32-plane segments, streaming
+    stores), FP32, every node against the FP64 oracle after 4 steps."""
+    w = wl.deformation_flow(n=256)
+    print(f"\n[case] CHE-only full field {w.shape} f32 4 steps", flush=True)
+    g = helpers.gpu_for(w, "f32")
+    g.step(4)
+    got = helpers.fields_of(g, False)
+    g.destroy()
+    o = helpers.oracle_for(w)
+    o.step(4)
+    _full_field_check(w, got, helpers.fields_of(o, False), "f32", F32_TOL)
+
+
 @pytest.mark.parametrize("model", ["mrt", "srt"])
 def test_zalesak_mrt_and_srt(model):
     """A small slotted sphere under rigid rotation (Eq. 37) with the MRT rates
