@@ -269,6 +269,7 @@ def main():
         for name, fn in (("mplb_copy_probe", lambda: mplb.mplb_copy_probe(a, b, nbytes)),
                          ("mplb_copy_probe_streaming", lambda: mplb.mplb_copy_probe(a, b, nbytes, 1)),
                          ("mplb_copy_probe_x4", lambda: mplb.mplb_copy_probe(a, b, nbytes, 2)),
+                         ("mplb_copy_probe_chunk256k", lambda: mplb.mplb_copy_probe(a, b, nbytes, 3)),
                          ("torch_copy", lambda: b.copy_(a))):
             for _ in range(3):
                 fn()

@@ -253,8 +253,10 @@ int mplb_time_stages(mplb_t* h, int nsteps, double ms[4]);
  * put beside the step's.  kind 0: one element per thread and round, ordinary
  * stores; 1: the same with non-temporal stores (the store policy of the step
  * kernels on large lattices); 2: four elements per thread and round,
- * non-temporal loads and stores, 16384 blocks of 256 threads.  Other kinds:
- * MPLB_E_INVAL.  Enqueues only. */
+ * non-temporal loads and stores, 16384 blocks of 256 threads; 3: each block of
+ * 256 threads streams its own contiguous 256 KB chunk, four elements per
+ * thread and round, non-temporal loads and stores (the fastest copy found on
+ * MI355X).  Other kinds: MPLB_E_INVAL.  Enqueues only. */
 int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hip_stream);
 
 /* Test hook: overwrite one stored population (set 0: f, 1: g; index i;

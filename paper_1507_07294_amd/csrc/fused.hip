@@ -761,6 +761,7 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   constexpr int NNODE = kTX * TY;
   constexpr int NHALO = NPHI - NNODE;
   static_assert(NHALO <= NTH, "one halo position per thread");
+  constexpr bool PRIO = sizeof(typename L::S) == 2;
   __shared__ T sphi[4][NPHI];
   __shared__ T sfq[2][7 * NNODE];  // the own nodes' pulled f of planes z, z+1
   const int lb = logical_block(blockIdx.x, gridDim.x);
@@ -837,12 +838,17 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   auto plane = [&](int z, auto pull) {
     constexpr bool PULL = decltype(pull)::value;
     const int zo = z * G.nx * G.ny;
+    // 16-bit storage: wave priority high from the stores of a plane until the
+    // pulls of the next are issued (256^3 with FP16 storage 190 -> 186 us per
+    // step; no change in FP32)
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
     // the history loads first: the memory counter retires in order
     T phip[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) phip[r] = own[r] ? ld_at(hist + zo, oxy[r]) : (T)0;
     Pending pd;
     if constexpr (PULL) issue(z + 2, pd);
+    if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -856,6 +862,7 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
       const T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
       T u[3], up[3];
       pcol[r].at(G, C, (const T*)B.ufield, gx, gy[r], z, zo + oxy[r], u, up);
+      if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
       st_at<NT>(hist + zo, oxy[r], phi);  // Eq. 34: only phi of this level is kept
       T dphiu[3];
 #pragma unroll
@@ -906,7 +913,8 @@ constexpr int coupled_ty() { return P == MPLB_F32 ? 16 : kTY; }
 
 // Segment length along z: enough blocks for a few rounds over the 256 CUs
 // (four rounds at two 8-row blocks per CU, two at one 16-row block), but long
-// segments where possible (each segment re-reads a few planes).
+// segments where possible (each segment re-reads a few planes).  `target`
+// overrides the block count aimed at.
 Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0) {
   Tiling t;
   t.tiles_x = (G.nx + kTX - 1) / kTX;
@@ -939,6 +947,14 @@ void launch_coupled(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, 
                        tl);
 }
 
+// The coupled step with 8-row tiles aims at 512 blocks, one round of the chip
+// at two blocks per CU, rather than four rounds: the ring's warm-up re-reads
+// five planes per segment, and on the 256 x 256 x 1024 box 256-plane
+// segments took FP16 1690 -> 1618 us per step, BF16 1665 -> 1624 and FP64
+// 5300 -> 5250 (1024 blocks: 1673, 1650, 5285), same bits.  The 16-row FP32
+// step keeps two rounds (one round: 2588 -> 2674 us).
+constexpr int kTarget8 = 512;
+
 // 16-row tiles only on a lattice that fills two rounds of the chip with them:
 // on small lattices (64^3: 16 blocks) they halve the blocks that run at all,
 // and 8-row tiles took 26 % less time per step on the serving trace's boxes.
@@ -966,7 +982,7 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
         return hipGetLastError();
       }
     }
-    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, 16), s);
+    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, 16, kTarget8), s);
   } else {
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)

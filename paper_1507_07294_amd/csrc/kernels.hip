@@ -340,6 +340,23 @@ __global__ void __launch_bounds__(kBlock) k_copy16_u4(const u32x4* __restrict__ 
   for (size_t i = full * 4 * T + tid; i < n; i += T) __builtin_nontemporal_store(__builtin_nontemporal_load(&a[i]), &b[i]);
 }
 
+// each block streams its own contiguous chunk of `chunk` elements, four per
+// thread and round, non-temporal both ways (the last chunk may be short)
+__global__ void __launch_bounds__(kBlock) k_copy16_chunk(const u32x4* __restrict__ a, u32x4* __restrict__ b, size_t n,
+                                                         size_t chunk) {
+  const size_t lo = (size_t)blockIdx.x * chunk;
+  const size_t hi = lo + chunk < n ? lo + chunk : n;
+  for (size_t i = lo + threadIdx.x; i < hi; i += 4 * kBlock) {
+    u32x4 v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * kBlock < hi) v[u] = __builtin_nontemporal_load(&a[i + u * kBlock]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (i + u * kBlock < hi) __builtin_nontemporal_store(v[u], &b[i + u * kBlock]);
+  }
+}
+
 __global__ void k_fill_int(int* p, int v, int count) {
   int i = blockIdx.x * kBlock + threadIdx.x;
   if (i < count) p[i] = v;
@@ -490,7 +507,12 @@ hipError_t launch_init(int P, int mode, const Geo& G, const Coef<double>& C, con
 }
 
 hipError_t launch_copy_probe(const void* src, void* dst, size_t bytes, int kind, hipStream_t s) {
-  if (kind == 2)
+  if (kind == 3) {
+    const size_t n = bytes / 16, chunk = (size_t)16384;  // 256 KB per block
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy16_chunk, dim3((unsigned)((n + chunk - 1) / chunk)), dim3(kBlock), 0, s,
+                       (const u32x4*)src, (u32x4*)dst, n, chunk);
+  } else if (kind == 2)
     hipLaunchKernelGGL(k_copy16_u4, dim3(16384), dim3(kBlock), 0, s, (const u32x4*)src, (u32x4*)dst, bytes / 16);
   else if (kind == 1)
     hipLaunchKernelGGL(k_copy16_nt, dim3(32768), dim3(kBlock), 0, s, (const u32x4*)src, (u32x4*)dst, bytes / 16);

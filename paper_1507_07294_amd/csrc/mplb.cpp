@@ -762,7 +762,7 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
 }
 
 int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hip_stream) {
-  if (!src || !dst || bytes % 16 || kind < 0 || kind > 2) return MPLB_E_INVAL;
+  if (!src || !dst || bytes % 16 || kind < 0 || kind > 3) return MPLB_E_INVAL;
   return launch_copy_probe(src, dst, bytes, kind, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK : MPLB_E_DEVICE;
 }
 

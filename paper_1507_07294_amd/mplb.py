@@ -353,7 +353,8 @@ def mplb_set_step_many_graphs(enable):
 def mplb_copy_probe(src, dst, nbytes, kind=0, stream=None):
     """Device copy with 16-byte accesses (bandwidth reference); src, dst are torch tensors.
     kind 0: one element per thread and round; 1: the same with non-temporal stores; 2: four
-    elements per thread and round, non-temporal loads and stores."""
+    elements per thread and round, non-temporal loads and stores; 3: each block streams its own
+    contiguous 256 KB chunk."""
     import torch
     s = torch.cuda.current_stream().cuda_stream if stream is None else stream
     rc = lib().mplb_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), C.c_size_t(nbytes),

@@ -154,7 +154,7 @@ def test_binding_uses_a_single_hip_runtime():
 
 def test_copy_probe_rejects_bad_arguments_before_any_device_call(lib):
     fake = C.c_void_p(4096)
-    assert lib.mplb_copy_probe(fake, fake, C.c_size_t(64), 3, None) == mplb.MPLB_E_INVAL
+    assert lib.mplb_copy_probe(fake, fake, C.c_size_t(64), 4, None) == mplb.MPLB_E_INVAL
     assert lib.mplb_copy_probe(fake, fake, C.c_size_t(64), -1, None) == mplb.MPLB_E_INVAL
     assert lib.mplb_copy_probe(fake, fake, C.c_size_t(60), 0, None) == mplb.MPLB_E_INVAL
     assert lib.mplb_copy_probe(None, fake, C.c_size_t(64), 0, None) == mplb.MPLB_E_INVAL

@@ -5,8 +5,8 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("kind", [0, 1, 2])
-@pytest.mark.parametrize("elems", [37, (1 << 24) + 37])
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+@pytest.mark.parametrize("elems", [37, (1 << 24) + 37, 3 * 16384])
 def test_copy_probe_is_exact(kind, elems):
     import torch
     from paper_1507_07294_amd import mplb
