@@ -253,7 +253,9 @@ def main():
                                                   / HBM_PEAK_GBPS, 4),
                            "k_step_ms": round(stc[2], 4), "k_achieved_GBps": round(kc, 1),
                            "k_frac": round(kc / HBM_PEAK_GBPS, 4),
-                           "traffic": measured_traffic("k_fused_che", f"deformation_flow_{n}^3", "f32")}
+                           "kernel": "k_fused_che2" if n >= 256 else "k_fused_che",
+                           "traffic": measured_traffic("k_fused_che2" if n >= 256 else "k_fused_che",
+                                                       f"deformation_flow_{n}^3", "f32")}
             lt.destroy()
             del lt
             torch.cuda.empty_cache()
