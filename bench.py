@@ -259,6 +259,19 @@ def main():
             lt.destroy()
             del lt
             torch.cuda.empty_cache()
+        # the same 256^3 step with 16-bit storage of f_1..f_6 (f_0 and phi of
+        # the previous level FP32): 40 B per update
+        wc = wl.deformation_flow(n=256)
+        lt = mplb.from_workload(wc, "f16")
+        dtc, stc = time_lattice(lt, args.steps, args.warmup)
+        result["che_only_256_f16"] = {"workload": "deformation_flow_256^3", "kernel": "k_fused_che2",
+                                      "MLUPS": round(wc.nodes * args.steps / dtc / 1e6, 1),
+                                      "ms_per_step": round(dtc / args.steps * 1e3, 4), "algorithmic_bytes_per_lup": 40,
+                                      "k_step_ms": round(stc[2], 4),
+                                      "k_frac": round(40 * wc.nodes / (stc[2] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        lt.destroy()
+        del lt
+        torch.cuda.empty_cache()
 
     if args.copy_probe:
         # bandwidth reference: the library's 16-byte copies (plain, streaming

@@ -156,9 +156,11 @@ int mplb_init(mplb_t* h, const double* phi0, const double* u0);
  * non-finite check (see mplb_set_check_interval) finds a NaN or Inf. */
 int mplb_step(mplb_t* h, int nsteps);
 
-/* Every k steps (k >= 1) mplb_step and mplb_step_many synchronise and check
- * that no population of the lattice became non-finite; k = 0 (default)
- * checks only when mplb_totals or mplb_check_finite is called. */
+/* Every k steps (k >= 1; 1000 for a new lattice) mplb_step and
+ * mplb_step_many synchronise and check that no population of the lattice
+ * became non-finite; k = 0 checks only when mplb_totals or mplb_check_finite
+ * is called (for callers that keep the stream asynchronous and check at their
+ * own synchronisation points). */
 int mplb_set_check_interval(mplb_t* h, int k);
 
 /* Synchronise the handle's stream and return MPLB_E_NONFINITE if a

@@ -77,6 +77,10 @@ bool valid_dims(int nx, int ny, int nz) {
 
 const uint64_t kMagic = 0x31303531504c424dULL;  // checkpoint tag
 
+// Steps between non-finite checks of a new lattice: a check is one 4-byte
+// copy and a synchronisation, which every 1000 steps costs well under 0.1 %.
+constexpr int kDefaultCheckInterval = 1000;
+
 struct CkptHeader {
   uint64_t magic;
   int32_t nx, ny, nz, prec, mode, pad;
@@ -100,7 +104,7 @@ struct mplb_s {
   bool have_params = false, have_init = false;
   Coef<double> C{};
   double velT = 1.0;
-  int check_interval = 0;
+  int check_interval = kDefaultCheckInterval;
   int tile_rows = 0;  // mplb_force_tile_rows (0: automatic)
   std::string err;
 };

@@ -134,6 +134,9 @@ class Server:
                 waiting.popleft()
                 with st.on_side():  # memory, upload and init on the side stream
                     lt = mplb.from_workload(req.workload, self.precision)  # returns initialised
+                # no synchronising checks inside the batched steps: each
+                # lattice's flag is read once it has finished (below)
+                lt.set_check_interval(0)
                 if self.on_admit is not None:
                     self.on_admit(req, lt)
                 lt.set_stream(st.main_ptr())

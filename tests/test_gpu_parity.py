@@ -477,6 +477,27 @@ def test_nonfinite_reported_with_step_index():
     assert rc == mplb.MPLB_E_NONFINITE
 
 
+def test_nonfinite_checked_every_1000_steps_by_default():
+    """A new lattice checks for non-finite populations every 1000 steps
+    without being asked: a NaN planted at step 10 is reported by the step
+    call that crosses step 1000, with that step in the message; interval 0
+    turns the checks off."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((8, 8, 8), (0, 0, 0), 42, coupled=True)
+    g = helpers.gpu_for(w, "f32")
+    g.step(10)
+    g.poke(0, 2, 100, float("nan"))
+    rc, _ = g.try_step(980)
+    assert rc == 0
+    rc, msg = g.try_step(20)
+    assert rc == mplb.MPLB_E_NONFINITE and "after step 1000" in msg
+    h = helpers.gpu_for(w, "f32")
+    h.set_check_interval(0)
+    h.poke(0, 2, 100, float("nan"))
+    rc, _ = h.try_step(1001)
+    assert rc == 0 and h.check_finite() == mplb.MPLB_E_NONFINITE
+
+
 @pytest.mark.parametrize("precision", ["f32", "f16", "f64"])
 def test_read_diagonal_is_the_x_equals_y_plane(precision):
     """mplb_read_diagonal gathers the plane x = y on the device: bitwise the

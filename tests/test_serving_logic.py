@@ -33,6 +33,9 @@ class FakeLattice:
     def set_stream(self, ptr):
         self.stream = ptr
 
+    def set_check_interval(self, k):
+        self.check_interval = k
+
     def destroy(self):
         self.alive = False
 
