@@ -265,6 +265,16 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hi
  * node n) of the current state with `value`, e.g. to plant a NaN. */
 int mplb_poke(mplb_t* h, int set, int i, long node, double value);
 
+/* Test hook (the NaN-poisoned halo check): fill with all-ones bytes (NaN in
+ * every storage type) the population arrays that the next step writes and
+ * the padding past the last node of every array it reads, and make every
+ * later step of this lattice fill its shared-memory rings and queues the same
+ * way before using them.  A node that a step does not write, a read past the
+ * last node, or a read of a shared-memory slot that no stage has written then
+ * shows as non-finite or changed fields.  Synchronises.  MPLB_E_STATE before
+ * init. */
+int mplb_poison(mplb_t* h);
+
 /* Test hook: the tile height of this lattice's step.  0 (default) lets
  * mplb_step choose: 16 rows on a lattice that fills at least 512 such tiles
  * for the coupled step with FP32 populations and for the CHE-only step in

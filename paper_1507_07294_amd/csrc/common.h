@@ -35,6 +35,7 @@ struct Coef {
   int stencil7;           // Eqs. 35-36 on the D3Q7 weights instead of D3Q15
   int forcing28;          // Gamma T of Eq. 28 instead of the printed Eq. 32 (D3Q15)
   int unit_rates;         // S^g = 1 off the stress moments 9..13 (the paper's choice)
+  int poison;             // test hook: the step kernels first fill their LDS with NaN bit patterns
 };
 
 // Compute type T, storage of f_0 (S0) and of f_1..f_6 and g (S).

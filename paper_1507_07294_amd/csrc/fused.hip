@@ -301,6 +301,14 @@ __device__ inline void grad_lds(const T* pm, const T* pc, const T* pp, int c, T 
   gr[2] = (T)(1.0 / 3.0) * (pp[c] - pm[c]) + (T)(1.0 / 24.0) * cz;
 }
 
+// Test hook (Coef::poison): fill shared memory with all-ones words, NaN in
+// every storage type, so that a read of a slot no stage has written shows in
+// the results.  Callers follow it with a barrier.
+__device__ inline void poison_shared(void* p, int bytes) {
+  uint32_t* w = (uint32_t*)p;
+  for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) w[i] = 0xffffffffu;
+}
+
 template <int P, int TY, int HALO>
 struct Ring {
   static constexpr int NT = kTX * TY;
@@ -480,6 +488,12 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   __shared__ T sphi[NPR][R::NPHI];
   __shared__ T smu[NMR][MU::NMU];
   __shared__ QT sfq[3][7 * R::NT];
+  if (C.poison) {
+    poison_shared(sphi, sizeof sphi);
+    poison_shared(smu, sizeof smu);
+    poison_shared(sfq, sizeof sfq);
+    __syncthreads();
+  }
   auto ps = [](int z) { return (z + 2 * NPR) % NPR; };  // z >= -2
   auto ms = [](int z) { return (z + 2 * NMR) % NMR; };  // z >= -2
   auto qs = [](int z) { return (z + 9) % 3; };
@@ -675,6 +689,11 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   using LD = PhiLoader<P, TY, 1, XYWALL, false>;
   __shared__ T sphi[4][R::NPHI];
   __shared__ T sfq[2][7 * R::NT];  // the own node's pulled f of planes z, z+1
+  if (C.poison) {
+    poison_shared(sphi, sizeof sphi);
+    poison_shared(sfq, sizeof sfq);
+    __syncthreads();
+  }
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
@@ -764,6 +783,11 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   constexpr bool PRIO = sizeof(typename L::S) == 2;
   __shared__ T sphi[4][NPHI];
   __shared__ T sfq[2][7 * NNODE];  // the own nodes' pulled f of planes z, z+1
+  if (C.poison) {
+    poison_shared(sphi, sizeof sphi);
+    poison_shared(sfq, sizeof sfq);
+    __syncthreads();
+  }
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
   const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
@@ -897,6 +921,7 @@ Coef<T> cast_coef_f(const Coef<double>& c) {
   o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
   o.stencil7 = c.stencil7; o.forcing28 = c.forcing28;
   o.unit_rates = c.unit_rates;
+  o.poison = c.poison;
   return o;
 }
 

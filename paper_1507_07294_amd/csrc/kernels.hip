@@ -388,6 +388,7 @@ Coef<T> cast_coef(const Coef<double>& c) {
   o.vel_kind = c.vel_kind; o.velU = (T)c.velU; o.vel_ct = (T)c.vel_ct; o.vel_ct_prev = (T)c.vel_ct_prev;
   o.stencil7 = c.stencil7; o.forcing28 = c.forcing28;
   o.unit_rates = c.unit_rates;
+  o.poison = c.poison;
   return o;
 }
 

@@ -780,6 +780,34 @@ int mplb_force_tile_rows(mplb_t* h, int rows) {
   return MPLB_OK;
 }
 
+int mplb_poison(mplb_t* h) {
+  if (!h) return MPLB_E_INVAL;
+  if (!h->have_init) return fail(h, MPLB_E_STATE, "poison before init");
+  const Plan& P = h->plan;
+  const size_t N = (size_t)h->G.N, pitch = P.pitch;
+  const bool pack = h->mode != MPLB_CHE_ONLY && store_size(h->prec) == 2;
+  const int q = h->mode == MPLB_COUPLED_Q19 ? 19 : 15;
+  // the level the next step writes: whole buffers
+  HIPCHK(h, hipMemsetAsync(h->B.f[1 - h->cur], 0xff, P.f, h->stream));
+  if (P.g) HIPCHK(h, hipMemsetAsync(h->B.g[1 - h->cur], 0xff, P.g, h->stream));
+  // the level it reads, and the history: the padding past the last node of every array
+  auto pad = [&](void* base, size_t first_elem, size_t elem) {
+    return hipMemsetAsync((char*)base + first_elem * elem, 0xff, (pitch - N) * elem, h->stream);
+  };
+  char* f = (char*)h->B.f[h->cur];
+  HIPCHK(h, pad(f, N, store0_size(h->prec)));
+  const size_t fi = pack ? 4 : store_size(h->prec);
+  for (int i = 1; i < 7; ++i) HIPCHK(h, pad(f + pitch * store0_size(h->prec), (size_t)(i - 1) * pitch + N, fi));
+  if (P.g)
+    for (int i = 0; i < (pack ? q - 6 : q); ++i)
+      HIPCHK(h, pad(h->B.g[h->cur], (size_t)i * pitch + N, store_size(h->prec)));
+  for (int a = 0; a < (h->mode != MPLB_CHE_ONLY ? 3 : 1); ++a)
+    HIPCHK(h, pad(h->B.phiu, (size_t)a * pitch + N, comp_size(h->prec)));
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  h->C.poison = 1;
+  return MPLB_OK;
+}
+
 int mplb_poke(mplb_t* h, int set, int i, long node, double value) {
   if (!h || set < 0 || set > 1 || i < 0 || node < 0 || node >= h->G.N) return MPLB_E_INVAL;
   const int q = h->mode == MPLB_COUPLED_Q19 ? 19 : 15;

@@ -87,6 +87,7 @@ def lib():
             "mplb_restore": (C.c_int, [vp, vp, sz]),
             "mplb_poke": (C.c_int, [vp, C.c_int, C.c_int, C.c_long, C.c_double]),
             "mplb_force_tile_rows": (C.c_int, [vp, C.c_int]),
+            "mplb_poison": (C.c_int, [vp]),
             "mplb_time_stages": (C.c_int, [vp, C.c_int, dp]),
             "mplb_copy_probe": (C.c_int, [vp, vp, sz, C.c_int, vp]),
             "mplb_destroy": (None, [vp]),
@@ -290,6 +291,11 @@ class Lattice:
 
     def poke(self, set_, i, node, value):
         self._chk(lib().mplb_poke(self._h, int(set_), int(i), int(node), float(value)))
+
+    def poison(self):
+        """Test hook: NaN-fill what the next step writes and the padding it must
+        not read, and have later steps NaN-fill their LDS first."""
+        self._chk(lib().mplb_poison(self._h))
 
     def force_tile_rows(self, rows):
         """Test hook: tile height of the coupled step (0 automatic, 8 or 16)."""
