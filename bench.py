@@ -268,7 +268,8 @@ def main():
                                       "MLUPS": round(wc.nodes * args.steps / dtc / 1e6, 1),
                                       "ms_per_step": round(dtc / args.steps * 1e3, 4), "algorithmic_bytes_per_lup": 40,
                                       "k_step_ms": round(stc[2], 4),
-                                      "k_frac": round(40 * wc.nodes / (stc[2] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
+                                      "k_frac": round(40 * wc.nodes / (stc[2] * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                      "traffic": measured_traffic("k_fused_che2", "deformation_flow_256^3", "f16")}
         lt.destroy()
         del lt
         torch.cuda.empty_cache()

@@ -135,16 +135,19 @@ __device__ inline __amdgpu_buffer_rsrc_t rsrc_at(const void* base) {
   // no stride, full 32-bit range, untyped 32-bit data (gfx9 descriptor word 3)
   return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, -1, 0x00020000);
 }
-template <class S>
+// NTL: non-temporal load (cache-policy bit 1), for data that no other block
+// reads again.
+template <class S, bool NTL = false>
 __device__ inline S ld_at(const S* base, int xy) {
   const uint32_t off = (uint32_t)xy * (uint32_t)sizeof(S);
+  constexpr int aux = NTL ? 2 : 0;
   if constexpr (sizeof(S) == 2) {
-    return __builtin_bit_cast(S, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(rsrc_at(base), off, 0, 0));
+    return __builtin_bit_cast(S, (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(rsrc_at(base), off, 0, aux));
   } else if constexpr (sizeof(S) == 4) {
-    return __builtin_bit_cast(S, (unsigned int)__builtin_amdgcn_raw_buffer_load_b32(rsrc_at(base), off, 0, 0));
+    return __builtin_bit_cast(S, (unsigned int)__builtin_amdgcn_raw_buffer_load_b32(rsrc_at(base), off, 0, aux));
   } else {
     static_assert(sizeof(S) == 8, "2, 4 or 8 bytes");
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rsrc_at(base), off, 0, 0));
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(rsrc_at(base), off, 0, aux));
   }
 }
 // NT: non-temporal (streaming) store, cache-policy bit 1.  It pays when a
@@ -559,7 +562,7 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
       if (own) {
         pull_gq_raw<P, PACK, XYWALL, Q>(G, gin, col, p, zo, col_xy, graw);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) hprev[a] = ld_at(hist + ((size_t)a * G.pitch + zo), col_xy);
+        for (int a = 0; a < 3; ++a) hprev[a] = ld_at<T, true>(hist + ((size_t)a * G.pitch + zo), col_xy);
       }
     }
     QT qv[7];
@@ -616,12 +619,16 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
     Macro<T> M;
     if constexpr (Q == 19) flow_macro19(C, g, phi, mu, gphi, lapmu, M);
     else flow_macro(C, g, phi, mu, gphi, lapmu, M);
+    // The history is read by its own node only: non-temporal loads leave L2
+    // to the lines that neighbouring tiles share (256 x 256 x 1024: FP32
+    // 2.589 -> 2.580 ms per step, FP16 1.626 -> 1.616, FP64 unchanged; the
+    // same hint on the g pulls, whose edge lines two tiles read, costs 3 %).
     T dphiu[3];
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       T pu = phi * M.u[a];
       T* h = hist + ((size_t)a * G.pitch + zo);
-      dphiu[a] = pu - (PACK ? hprev[a] : ld_at(h, col_xy));
+      dphiu[a] = pu - (PACK ? hprev[a] : ld_at<T, true>(h, col_xy));
       st_at<NT>(h, col_xy, pu);
     }
     collide_che(C, f, phi, mu, M.u, dphiu);
@@ -762,22 +769,28 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   plane(z1 - 1, std::false_type{});
 }
 
-// CHE-only with two rows per thread: a block of 64 x 8 threads owns a
-// 64 x 16 tile, thread (tx, ty) the nodes of rows ty and ty + 8.  The ring's
-// halo of one falls from 29 % to 16 % of the tile's own pulls, each wave has
-// twice the loads in flight per plane, and the LDS (a 4-plane phi ring and a
-// 2-plane queue for 1024 nodes, 76 KB in FP32) still lets two blocks share a
-// CU.  Otherwise the march of k_fused_che: at plane z the pulls of plane z+2
-// are issued, plane z is finished while they are in flight, and their phi
+// CHE-only with two nodes per thread: a block of 64 x 8 threads owns a
+// tile of 1024 nodes, TW wide.  TW = 128: a 128 x 8 tile, thread (tx, ty)
+// the nodes tx and tx + 64 of row ty; TW = 64: a 64 x 16 tile, thread
+// (tx, ty) the nodes of rows ty and ty + 8.  Each wave has twice the loads of
+// k_fused_che in flight per plane, and the LDS (a 4-plane phi ring and a
+// 2-plane queue for 1024 nodes, 76-78 KB in FP32) still lets two blocks share
+// a CU.  The wide tile pulls more halo nodes (27 % of its own against 16 %)
+// but its halo columns, each x neighbour in a cache line of its own, cover 20
+// rows instead of 36: on 256^3 it takes 236 -> 227 us per step in FP32 and
+// 186 -> 176 us with FP16 storage, on 200 x 136 x 300 203 -> 177 us (same
+// bits).  Otherwise the march of k_fused_che: at plane z the pulls of plane
+// z+2 are issued, plane z is finished while they are in flight, and their phi
 // goes into the ring before the one barrier of the plane.
-template <int P, bool XYWALL, bool NT, int V = 0>
+template <int P, bool XYWALL, bool NT, int V = 0, int TW = 128>
 __global__ void __launch_bounds__(kTX * 8) __attribute__((amdgpu_waves_per_eu(waves_per_eu<P>())))
 k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
+  static_assert(TW == 64 || TW == 128, "64 x 16 or 128 x 8 tiles");
   using T = typename Prec<P>::T;
   using L = Lat<P, false>;
-  constexpr int TY = 16, NTH = kTX * 8;
-  constexpr int PX = kTX + 2, PY = TY + 2, NPHI = PX * PY;
-  constexpr int NNODE = kTX * TY;
+  constexpr int TY = 1024 / TW, NTH = kTX * 8;
+  constexpr int PX = TW + 2, PY = TY + 2, NPHI = PX * PY;
+  constexpr int NNODE = TW * TY;
   constexpr int NHALO = NPHI - NNODE;
   static_assert(NHALO <= NTH, "one halo position per thread");
   constexpr bool PRIO = sizeof(typename L::S) == 2;
@@ -790,28 +803,29 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   }
   const int lb = logical_block(blockIdx.x, gridDim.x);
   const int tile = lb % (TL.tiles_x * TL.tiles_y), seg = lb / (TL.tiles_x * TL.tiles_y);
-  const int x0 = (tile % TL.tiles_x) * kTX, y0 = (tile / TL.tiles_x) * TY;
+  const int x0 = (tile % TL.tiles_x) * TW, y0 = (tile / TL.tiles_x) * TY;
   const int z0 = seg * TL.lz, z1 = min(G.nz, z0 + TL.lz);
   const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-  const int gx = x0 + tx;
   const void* fin = B.f[cur];
   void* fo = B.f[1 - cur];
   T* hist = (T*)B.phiu;
   // own nodes (a node outside the lattice maps onto its periodic image or
   // its mirror at a wall, whose phi the ring needs there)
   Column oc[2];
-  int oxy[2], olds[2], gy[2];
+  int oxy[2], olds[2], gx[2], gy[2];
   bool own[2];
   PrescColumn<T> pcol[2];
 #pragma unroll
   for (int r = 0; r < 2; ++r) {
-    gy[r] = y0 + ty + 8 * r;
-    own[r] = gx < G.nx && gy[r] < G.ny;
-    const int mx = map_axis(gx, G.nx, G.wall_x), my = map_axis(gy[r], G.ny, G.wall_y);
+    const int lx = TW == 64 ? tx : tx + 64 * r, ly = TW == 64 ? ty + 8 * r : ty;
+    gx[r] = x0 + lx;
+    gy[r] = y0 + ly;
+    own[r] = gx[r] < G.nx && gy[r] < G.ny;
+    const int mx = map_axis(gx[r], G.nx, G.wall_x), my = map_axis(gy[r], G.ny, G.wall_y);
     oc[r] = make_column<XYWALL>(G, mx, my);
     oxy[r] = mx + G.nx * my;
-    olds[r] = (ty + 8 * r + 1) * PX + tx + 1;
-    pcol[r].init(G, C, gx, gy[r]);
+    olds[r] = (ly + 1) * PX + lx + 1;
+    pcol[r].init(G, C, gx[r], gy[r]);
   }
   // one halo position for each of the first NHALO threads
   const bool hon = threadIdx.x < NHALO;
@@ -866,10 +880,13 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     // pulls of the next are issued (256^3 with FP16 storage 190 -> 186 us per
     // step; no change in FP32)
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
-    // the history loads first: the memory counter retires in order
+    // the history loads first: the memory counter retires in order.  No
+    // other block reads them, so they are non-temporal and leave L2 to the
+    // halo pulls that neighbouring tiles share (256^3: 227 -> 225 us per
+    // step in FP32, 176 -> 171 us with FP16 storage).
     T phip[2];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) phip[r] = own[r] ? ld_at(hist + zo, oxy[r]) : (T)0;
+    for (int r = 0; r < 2; ++r) phip[r] = own[r] ? ld_at<T, true>(hist + zo, oxy[r]) : (T)0;
     Pending pd;
     if constexpr (PULL) issue(z + 2, pd);
     if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
@@ -885,7 +902,7 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
                                    (V & kVarS7) != 0);
       const T mu = 4 * C.beta * phi * (phi - 1) * (phi + 1) - C.kappa * lap;
       T u[3], up[3];
-      pcol[r].at(G, C, (const T*)B.ufield, gx, gy[r], z, zo + oxy[r], u, up);
+      pcol[r].at(G, C, (const T*)B.ufield, gx[r], gy[r], z, zo + oxy[r], u, up);
       if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
       st_at<NT>(hist + zo, oxy[r], phi);  // Eq. 34: only phi of this level is kept
       T dphiu[3];
@@ -940,9 +957,9 @@ constexpr int coupled_ty() { return P == MPLB_F32 ? 16 : kTY; }
 // (four rounds at two 8-row blocks per CU, two at one 16-row block), but long
 // segments where possible (each segment re-reads a few planes).  `target`
 // overrides the block count aimed at.
-Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0) {
+Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0, int TW = kTX) {
   Tiling t;
-  t.tiles_x = (G.nx + kTX - 1) / kTX;
+  t.tiles_x = (G.nx + TW - 1) / TW;
   t.tiles_y = (G.ny + TY - 1) / TY;
   int cols = t.tiles_x * t.tiles_y;
   if (target <= 0) target = TY >= 16 ? 512 : 2048;
@@ -985,15 +1002,17 @@ constexpr int kTarget8 = 512;
 // and 8-row tiles took 26 % less time per step on the serving trace's boxes.
 constexpr int kMinBlocksTall = 512;
 
-// CHE-only tiling.  Two rows per thread (k_fused_che2, 64 x 16 tiles) with
+// CHE-only tiling.  Two nodes per thread (k_fused_che2, 128 x 8 tiles) with
 // segments sized for 512 blocks, one round of the chip at two blocks per CU
 // (32-plane segments at 256^3), wherever a lattice fills that many; 8-row
-// tiles (k_fused_che) otherwise and for FP64, whose two-row LDS would not let
-// two blocks share a CU.  Measured on 256^3 (FP32): 254 -> 236 us per step
-// (8-row tiles with 32-plane segments: 248; two rows with 8- or 16-plane
-// segments: 245, 238); FP16 storage 219 -> 190 us; 128^3 unchanged (33 us),
-// where two-row tiles would halve the blocks.  Same bits in every variant.
+// tiles of 64 (k_fused_che) otherwise and for FP64, whose two-node LDS would
+// not let two blocks share a CU.  Measured on 256^3 (FP32, 64 x 16 tiles for
+// the two-node kernel): 254 -> 236 us per step (8-row tiles with 32-plane
+// segments: 248; two rows with 8- or 16-plane segments: 245, 238); FP16
+// storage 219 -> 190 us; 128^3 unchanged (33 us), where two-node tiles would
+// halve the blocks.  Same bits in every variant.
 constexpr int kCheTarget2 = 512, kCheMinLz2 = 8, kCheMinBlocks2 = 512;
+constexpr int kCheTW = 128;
 
 template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
@@ -1012,10 +1031,10 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
     // the CHE-only ring re-reads only 2 planes per segment: shorter segments
     // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
     if constexpr (sizeof(typename Prec<P>::T) == 4) {
-      Tiling t2 = make_tiling(G, 16, kCheMinLz2, kCheTarget2);
+      Tiling t2 = make_tiling(G, 1024 / kCheTW, kCheMinLz2, kCheTarget2, kCheTW);
       if (rows == 16 || (rows == 0 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2)) {
-        hipLaunchKernelGGL((k_fused_che2<P, XYWALL, NT, V & kVarS7>), dim3((unsigned)(t2.tiles_x * t2.tiles_y * t2.nseg)),
-                           dim3(kTX * 8), 0, s, G, C, B, cur, t2);
+        hipLaunchKernelGGL((k_fused_che2<P, XYWALL, NT, V & kVarS7, kCheTW>),
+                           dim3((unsigned)(t2.tiles_x * t2.tiles_y * t2.nseg)), dim3(kTX * 8), 0, s, G, C, B, cur, t2);
         return hipGetLastError();
       }
     }

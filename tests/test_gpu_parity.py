@@ -417,12 +417,13 @@ def _che_velocity(w, kind, rng):
 @pytest.mark.parametrize("kind,shape,bc,seed", [("deformation", (70, 37, 29), (0, 0, 0), 31),
                                                 ("field", (65, 17, 40), (1, 1, 1), 32),
                                                 ("zalesak", (130, 20, 24), (0, 1, 0), 33)])
-def test_che_only_two_row_tiles(precision, tol, kind, shape, bc, seed):
-    """The CHE-only kernel with two rows per thread (64 x 16 tiles; forced
+def test_che_only_two_node_tiles(precision, tol, kind, shape, bc, seed):
+    """The CHE-only kernel with two nodes per thread (128 x 8 tiles; forced
     here, chosen by itself on lattices of at least 512 such tiles) against
-    the oracle after 30 steps, and bitwise against 8-row tiles: ragged tiles
-    in x and y, walls on every axis or on y only."""
-    print(f"\n[case] CHE two-row tiles {kind} {shape} bc={bc} {precision}", flush=True)
+    the oracle after 30 steps, and bitwise against 8-row tiles of 64: ragged
+    tiles in x (70 and 65 of 128 columns, 130 = 128 + 2) and y, walls on
+    every axis or on y only."""
+    print(f"\n[case] CHE two-node tiles {kind} {shape} bc={bc} {precision}", flush=True)
     w = _che_velocity(wl.perturbed_case(shape, bc, seed, coupled=False), kind, np.random.default_rng(seed))
     o = helpers.oracle_for(w)
     o.step(30)
@@ -444,8 +445,9 @@ def test_che_only_two_row_tiles(precision, tol, kind, shape, bc, seed):
 
 def test_che_only_256_full_field():
     """The 256^3 interface-tracking box in the launch configuration the
-    benchmark times (two rows per thread, 32-plane segments, streaming
-    stores), FP32, every node against the FP64 oracle after 4 steps."""
+    benchmark times (two nodes per thread on 128 x 8 tiles, 32-plane
+    segments, streaming stores), FP32, every node against the FP64 oracle
+    after 4 steps."""
     w = wl.deformation_flow(n=256)
     print(f"\n[case] CHE-only full field {w.shape} f32 4 steps", flush=True)
     g = helpers.gpu_for(w, "f32")
