@@ -87,8 +87,9 @@ def _axis_window(c, n, r, wall):
 
 def window_oracle_fields(w, node_xyz, steps):
     """Oracle fields at `node_xyz` after `steps` steps, computed on a window
-    (coupled lattices: the prescribed velocities depend on absolute position)."""
-    assert w.coupled
+    (coupled lattices, and CHE-only lattices at rest: the step is then the same
+    at every node, while a prescribed flow depends on absolute position)."""
+    assert w.coupled or (w.velocity or {"kind": "zero"})["kind"] == "zero"
     r = 3 * steps + 4
     nx, ny, nz = w.shape
     x, y, z = node_xyz
