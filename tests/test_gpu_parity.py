@@ -107,6 +107,32 @@ def test_coupled_q19_f32(shape, bc, seed):
     _compare(w, [1, 10, 100], "f32", F32_TOL)
 
 
+DEGENERATE = {"no_surface_tension": dict(sigma=0.0), "no_mobility": dict(mobility=0.0),
+              "equal_densities": dict(ratio=1.0), "at_rest": dict(u_amp=0.0, gravity=(0.0, 0.0, 0.0))}
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+@pytest.mark.parametrize("case", list(DEGENERATE))
+def test_degenerate_parameters(case, precision, tol):
+    """Degenerate parameter sets of the model against the oracle after 1 and
+    20 steps (24 x 20 x 18, walls in z): sigma = 0 (beta = kappa = 0, so
+    mu = 0 everywhere and neither the surface-tension force nor the chemical
+    diffusion acts), mobility 0 (eta = 0 in Eq. 5: phi is carried by the flow
+    alone), equal densities (the density gradient and F_a vanish), and a
+    fluid at rest without gravity (the interface alone drives the flow)."""
+    w = wl.perturbed_case((24, 20, 18), (0, 0, 1), 61, coupled=True, **DEGENERATE[case])
+    _compare(w, [1, 20], precision, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", F64_TOL), ("f32", F32_TOL)])
+def test_che_only_without_mobility(precision, tol):
+    """The CHE-only step with mobility 0 under the deformation flow of Eq. 41
+    (phi carried by the prescribed flow alone) against the oracle."""
+    w = wl.deformation_flow(n=24)
+    w.params = w.params.replace(mobility=0.0)
+    _compare(w, [1, 30], precision, tol, coupled=False)
+
+
 @pytest.mark.parametrize("q", [15, 19])
 def test_f32_tall_tiles_with_side_walls(q):
     """The FP32 step takes 16-row tiles only on a lattice of at least 512 such
