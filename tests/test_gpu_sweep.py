@@ -104,3 +104,56 @@ def test_random_case(case):
         p_err = helpers.rel_err(got["p"], ref["p"], max(FLOOR, float(un / np.sqrt(n))))
         print(f"  p against the flow speed: {p_err:.2e}", flush=True)
         assert p_err <= lim("p"), ("p", p_err)
+
+
+def _batches(n=12, seed=20261204):
+    """Batches of 2-8 coupled D3Q15 lattices of random small shapes and walls
+    in one precision, some advanced by one step first (so that the batch
+    holds both step parities), then 1-7 batched steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for b in range(n):
+        prec = ("f64", "f32", "f16", "bf16")[b % 4]
+        items = []
+        for _ in range(int(rng.integers(2, 9))):
+            while True:
+                shape = (_axis(rng), _axis(rng), _axis(rng))
+                if shape[0] * shape[1] * shape[2] <= 40000:
+                    break
+            items.append((shape, tuple(int(v) for v in rng.integers(0, 2, 3)), int(rng.integers(0, 1000)),
+                          int(rng.integers(0, 2))))
+        out.append((b, prec, tuple(items), int(rng.integers(1, 8)), bool(rng.integers(0, 2))))
+    return out
+
+
+BATCHES = _batches()
+
+
+@pytest.mark.parametrize("case", BATCHES, ids=[f"b{c[0]}-{c[1]}-{len(c[2])}" for c in BATCHES])
+def test_random_batch(case):
+    """Every lattice of a batched step (graph-replayed or launched one by
+    one) is bitwise the same lattice stepped alone."""
+    from paper_1507_07294_amd import mplb
+    b, prec, items, steps, graphs = case
+    print(f"\n[case] batch {b}: {prec} steps={steps} graphs={graphs} "
+          + " ".join(f"{'x'.join(map(str, s))}/{bc}/+{pre}" for s, bc, _, pre in items), flush=True)
+    ws = [_workload("coupled", s, bc, None, sd) for s, bc, sd, _ in items]
+    alone = []
+    for w, (_, _, _, pre) in zip(ws, items):
+        g = helpers.gpu_for(w, prec)
+        g.step(pre + steps)
+        alone.append(helpers.fields_of(g, True))
+        g.destroy()
+    lats = [helpers.gpu_for(w, prec) for w in ws]
+    for g, (_, _, _, pre) in zip(lats, items):
+        g.step(pre)
+    mplb.mplb_set_step_many_graphs(graphs)
+    try:
+        mplb.mplb_step_many(lats, steps)
+    finally:
+        mplb.mplb_set_step_many_graphs(True)
+    for i, (g, a) in enumerate(zip(lats, alone)):
+        got = helpers.fields_of(g, True)
+        g.destroy()
+        for k in got:
+            assert np.array_equal(got[k], a[k]), (i, items[i][0], k)
