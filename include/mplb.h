@@ -276,11 +276,11 @@ int mplb_poke(mplb_t* h, int set, int i, long node, double value);
 int mplb_poison(mplb_t* h);
 
 /* Test hook: the tile height of this lattice's step.  0 (default) lets
- * mplb_step choose: 16 rows on a lattice that fills at least 512 such tiles
- * for the coupled step with FP32 populations, and for the CHE-only step in
- * FP32 compute (any storage) the kernel in which a thread owns two nodes of
- * a 128 x 8 tile, 8 otherwise.  8 or 16 forces one (16 where it exists,
- * else MPLB_E_INVAL).  The tiling
+ * mplb_step choose: 16 rows for the coupled step with FP32 populations on a
+ * lattice that fills 512 such blocks, and for the CHE-only step in FP32
+ * compute (any storage) the kernel in which a thread owns two nodes of a
+ * 128 x 8 tile on a lattice that fills at least 384 of those; 8 otherwise.
+ * 8 or 16 forces one (16 where it exists, else MPLB_E_INVAL).  The tiling
  * changes which work a block does, not the arithmetic of a node, so the
  * fields are bitwise the same; mplb_step_many always uses 8 rows. */
 int mplb_force_tile_rows(mplb_t* h, int rows);

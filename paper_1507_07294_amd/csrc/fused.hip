@@ -963,7 +963,14 @@ Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0, int TW = kT
   t.tiles_y = (G.ny + TY - 1) / TY;
   int cols = t.tiles_x * t.tiles_y;
   if (target <= 0) target = TY >= 16 ? 512 : 2048;
-  int want = (target + cols - 1) / cols;
+  // at most `target` blocks: the blocks of a round that the chip cannot
+  // start with the others run after them, alone.  Rounding the segment count
+  // down instead of up took 160 x 160 x 640 from 0.704 to 0.499 ms per step
+  // with FP16 populations, 192 x 192 x 768 from 0.972 to 0.726 ms, and a
+  // 224^3 CHE-only step from 210 to 168 us (same bits; the boxes whose
+  // planes divide the target evenly, such as 256 x 256 x 1024, unchanged).
+  int want = target / cols;
+  if (want < 1) want = 1;
   int lz = (G.nz + want - 1) / want;
   if (lz < min_lz) lz = min_lz;
   if (lz > G.nz) lz = G.nz;
@@ -1000,18 +1007,24 @@ constexpr int kTarget8 = 512;
 // 16-row tiles only on a lattice that fills two rounds of the chip with them:
 // on small lattices (64^3: 16 blocks) they halve the blocks that run at all,
 // and 8-row tiles took 26 % less time per step on the serving trace's boxes.
+// With the segment count rounded down, that is a lattice whose tile count
+// divides the 512 blocks (256 x 256 x 1024: 2.59 ms against 2.87 with 8
+// rows); elsewhere 8 rows are as fast or faster (192 x 192 x 768: 1.168 ms
+// against 1.171, 160 x 160 x 640: 0.712 against 0.762).
 constexpr int kMinBlocksTall = 512;
 
 // CHE-only tiling.  Two nodes per thread (k_fused_che2, 128 x 8 tiles) with
-// segments sized for 512 blocks, one round of the chip at two blocks per CU
-// (32-plane segments at 256^3), wherever a lattice fills that many; 8-row
-// tiles of 64 (k_fused_che) otherwise and for FP64, whose two-node LDS would
-// not let two blocks share a CU.  Measured on 256^3 (FP32, 64 x 16 tiles for
-// the two-node kernel): 254 -> 236 us per step (8-row tiles with 32-plane
-// segments: 248; two rows with 8- or 16-plane segments: 245, 238); FP16
-// storage 219 -> 190 us; 128^3 unchanged (33 us), where two-node tiles would
-// halve the blocks.  Same bits in every variant.
-constexpr int kCheTarget2 = 512, kCheMinLz2 = 8, kCheMinBlocks2 = 512;
+// segments sized for at most 512 blocks, one round of the chip at two blocks
+// per CU (32-plane segments at 256^3), wherever a lattice fills at least 384
+// of them; 8-row tiles of 64 (k_fused_che) otherwise and for FP64, whose
+// two-node LDS would not let two blocks share a CU.  Measured (FP32, us per
+// step, two-node against 8-row tiles): 256^3 232 against 262, 224^3 168
+// against 205, 192^3 124 against 129, 160^3 (480 blocks) 73 against 72,
+// 128^3 (256 blocks) 35.5 against 33.  Before the two-node kernel took
+// 128 x 8 tiles, on 256^3 with 64 x 16 tiles: 254 -> 236 us (8-row tiles with
+// 32-plane segments: 248; two rows with 8- or 16-plane segments: 245, 238),
+// FP16 storage 219 -> 190 us.  Same bits in every variant.
+constexpr int kCheTarget2 = 512, kCheMinLz2 = 8, kCheMinBlocks2 = 384;
 constexpr int kCheTW = 128;
 
 template <int P, bool XYWALL, bool NT, int V>
