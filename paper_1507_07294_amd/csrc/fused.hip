@@ -953,10 +953,10 @@ constexpr int kTY = 8;
 template <int P>
 constexpr int coupled_ty() { return P == MPLB_F32 ? 16 : kTY; }
 
-// Segment length along z: enough blocks for a few rounds over the 256 CUs
-// (four rounds at two 8-row blocks per CU, two at one 16-row block), but long
-// segments where possible (each segment re-reads a few planes).  `target`
-// overrides the block count aimed at.
+// Segment length along z: at most the blocks of a few rounds over the 256 CUs
+// (four rounds at two 8-row blocks per CU, two at one 16-row block), with
+// segments as long as that allows (each segment re-reads a few planes).
+// `target` overrides the block count aimed at.
 Tiling make_tiling(const Geo& G, int TY, int min_lz, int target = 0, int TW = kTX) {
   Tiling t;
   t.tiles_x = (G.nx + TW - 1) / TW;
