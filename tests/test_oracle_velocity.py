@@ -8,7 +8,9 @@ their formulas:
 * Sec. III B, Eq. 41: an incompressible field whose time factor cos(pi t/T)
   stops it at T/2 and reverses it, with t the step count divided by L/U;
 * both: the CHE-only step under these fields brings the interface back after
-  one period, with an Eq. 40 error that falls as the lattice is refined.
+  one period, with an Eq. 40 error that falls as the lattice is refined;
+* Sec. III A's comparison: on Zalesak's sphere the SRT model loses stability
+  at Pe = 600 where the MRT model does not.
 """
 import numpy as np
 import pytest
@@ -160,3 +162,27 @@ def test_zalesak_one_revolution_returns():
     o.step(1600)
     err = ist.err_eq40(o.read("phi"), w.phi0)
     assert err < 0.04
+
+
+@pytest.mark.slow
+def test_zalesak_srt_loses_stability_where_mrt_does_not():
+    """The paper's comparison on Zalesak's sphere (Sec. III A): the SRT model
+    (every rate s_1 of Eq. 38) loses stability at Pe = 600 while the MRT
+    model does not, and at Pe = 200, where both are stable, MRT is the more
+    accurate.  On the sphere scaled to 32^3 over one revolution: Pe = 600
+    MRT phi within [-1.29, 1.28] (Err 0.038), SRT [-6.9, 4.8] (Err 0.19);
+    Pe = 200 Err 0.027 (MRT) against 0.030 (SRT)."""
+    import dataclasses
+    res = {}
+    for Pe in (200, 600):
+        for model in ("mrt", "srt"):
+            w = wl.zalesak(n=32, R=12.8, slot=5.12, Pe=Pe)
+            if model == "srt":
+                w.params = dataclasses.replace(w.params, s_f=ist.srt_rates(w.params.s_f))
+            o = helpers.oracle_for(w)
+            o.step(3200)
+            phi = o.read("phi")
+            res[Pe, model] = (float(np.abs(phi).max()), ist.err_eq40(phi, w.phi0))
+    assert res[600, "mrt"][0] < 1.5 and res[600, "srt"][0] > 3.0, res   # bounded against blown up
+    assert res[600, "srt"][1] > 3 * res[600, "mrt"][1], res
+    assert res[200, "srt"][0] < 1.5 and res[200, "mrt"][1] < res[200, "srt"][1], res
