@@ -150,7 +150,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); a lattice larger than one "
-              "GPU would be split into z-slabs with halo exchange, which this build does not include.",
+              "GPU would be split into z-slabs with a halo exchange, which the library does not implement.",
               file=sys.stderr)
         sys.exit(2)
     import torch
