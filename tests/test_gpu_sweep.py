@@ -157,3 +157,51 @@ def test_random_batch(case):
         g.destroy()
         for k in got:
             assert np.array_equal(got[k], a[k]), (i, items[i][0], k)
+
+
+def _midsize(n=8, seed=20261205):
+    """Boxes of 5-30 M nodes where the library has two kernels to choose from
+    and the automatic tiling rounds its segment count down to stay within its
+    block target: CHE-only boxes with random sides (FP32 compute, FP32 or
+    FP16 storage; two-node 128 x 8 tiles from 384 blocks), and coupled FP32
+    boxes whose 64 x 16 tile count divides 512 (ragged sides within those
+    tiles), which take 16-row tiles."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n):
+        if k % 2 == 0:
+            mode, prec = "che", ("f32", "f16")[(k // 2) % 2]
+            while True:
+                shape = (int(rng.integers(100, 261)), int(rng.integers(100, 261)), int(rng.integers(100, 601)))
+                if 5e6 <= shape[0] * shape[1] * shape[2] <= 3e7:
+                    break
+        else:
+            mode, prec = "coupled", "f32"
+            tx, ty = (int(v) for v in rng.choice([(2, 8), (4, 8), (2, 16), (4, 4)]))
+            nz = 16 * (512 // (tx * ty)) + int(rng.integers(0, 200))
+            shape = (int(rng.integers(64 * tx - 50, 64 * tx + 1)), int(rng.integers(16 * ty - 12, 16 * ty + 1)), nz)
+        out.append((k, mode, prec, shape, tuple(int(v) for v in rng.integers(0, 2, 3)), int(rng.integers(0, 1000))))
+    return out
+
+
+MIDSIZE = _midsize()
+
+
+@pytest.mark.parametrize("case", MIDSIZE, ids=[f"m{c[0]}-{c[1]}-{c[2]}-{'x'.join(map(str, c[3]))}" for c in MIDSIZE])
+def test_midsize_automatic_tiling_equals_8_rows(case):
+    """The library's own choice of tiles and segments on a mid-size box gives
+    bitwise the fields of the same box forced onto 8-row tiles of 64."""
+    k, mode, prec, shape, bc, seed = case
+    print(f"\n[case] midsize {k}: {mode} {prec} {shape} bc={bc}", flush=True)
+    w = _workload(mode, shape, bc, "deformation" if mode == "che" else None, seed)
+    coupled = mode != "che"
+    out = []
+    for rows in (0, 8):
+        g = helpers.gpu_for(w, prec)
+        if rows:
+            g.force_tile_rows(rows)
+        g.step(3)
+        out.append(helpers.fields_of(g, coupled))
+        g.destroy()
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f]), f
