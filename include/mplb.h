@@ -279,7 +279,8 @@ int mplb_poison(mplb_t* h);
  * mplb_step choose: 16 rows for the coupled step with FP32 populations on a
  * lattice that fills 512 such blocks, and for the CHE-only step in FP32
  * compute (any storage) the kernel in which a thread owns two nodes of a
- * 128 x 8 tile on a lattice that fills at least 384 of those; 8 otherwise.
+ * 128 x 8 tile on a lattice of at least 5 million nodes that fills at least
+ * 384 of those; 8 otherwise.
  * 8 or 16 forces one (16 where it exists, else MPLB_E_INVAL).  The tiling
  * changes which work a block does, not the arithmetic of a node, so the
  * fields are bitwise the same; mplb_step_many always uses 8 rows. */

@@ -1013,18 +1013,25 @@ constexpr int kTarget8 = 512;
 // against 1.171, 160 x 160 x 640: 0.712 against 0.762).
 constexpr int kMinBlocksTall = 512;
 
-// CHE-only tiling.  Two nodes per thread (k_fused_che2, 128 x 8 tiles) with
-// segments sized for at most 512 blocks, one round of the chip at two blocks
-// per CU (32-plane segments at 256^3), wherever a lattice fills at least 384
-// of them; 8-row tiles of 64 (k_fused_che) otherwise and for FP64, whose
-// two-node LDS would not let two blocks share a CU.  Measured (FP32, us per
-// step, two-node against 8-row tiles): 256^3 232 against 262, 224^3 168
-// against 205, 192^3 124 against 129, 160^3 (480 blocks) 73 against 72,
-// 128^3 (256 blocks) 35.5 against 33.  Before the two-node kernel took
-// 128 x 8 tiles, on 256^3 with 64 x 16 tiles: 254 -> 236 us (8-row tiles with
+// CHE-only tiling.  Both kernels size their segments for at most 512
+// blocks, one round of the chip at two blocks per CU.  Two nodes per thread
+// (k_fused_che2, 128 x 8 tiles, segments of at least 8 planes: 32 at 256^3)
+// on lattices of at least 5 M nodes that fill at least 384 such blocks; 8-row
+// tiles of 64 (k_fused_che, segments of at least 5 planes) otherwise and for
+// FP64, whose two-node LDS would not let two blocks share a CU.  Measured
+// (FP32, us per step, one-node against two-node tiles): 96^3 23.9 / 30.2,
+// 128^3 32.6 / 35.3, 144^3 51.4 / 61.4, 160^3 61.9 / 71.2, 176^3 106.8 /
+// 100.4, 192^3 115.0 / 119.3, 224^3 198 / 161; 256^3 262 / 232 with the
+// earlier one-node sizing.  The
+// one-node kernel took four rounds with segments of at least 8 planes before
+// (96^3 30.5, 100^3 30.6, 144^3 54.9, 160^3 67.9, 192^3 124.4 us; 128^3, one
+// round either way, unchanged).  Before the two-node kernel took 128 x 8
+// tiles, on 256^3 with 64 x 16 tiles: 254 -> 236 us (8-row tiles with
 // 32-plane segments: 248; two rows with 8- or 16-plane segments: 245, 238),
 // FP16 storage 219 -> 190 us.  Same bits in every variant.
 constexpr int kCheTarget2 = 512, kCheMinLz2 = 8, kCheMinBlocks2 = 384;
+constexpr int kCheMinNodes2 = 5000000;
+constexpr int kCheTarget1 = 512, kCheMinLz1 = 5;
 constexpr int kCheTW = 128;
 
 template <int P, bool XYWALL, bool NT, int V>
@@ -1041,17 +1048,18 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
     }
     launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, 16, kTarget8), s);
   } else {
-    // the CHE-only ring re-reads only 2 planes per segment: shorter segments
-    // fill the chip better on small boxes (128^3: 41.7 -> 35.4 us per step)
+    // the CHE-only ring re-reads only 2 planes per segment, so its segments
+    // can be shorter than the coupled step's and fill the chip on small boxes
     if constexpr (sizeof(typename Prec<P>::T) == 4) {
       Tiling t2 = make_tiling(G, 1024 / kCheTW, kCheMinLz2, kCheTarget2, kCheTW);
-      if (rows == 16 || (rows == 0 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2)) {
+      if (rows == 16 ||
+          (rows == 0 && G.N >= kCheMinNodes2 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2)) {
         hipLaunchKernelGGL((k_fused_che2<P, XYWALL, NT, V & kVarS7, kCheTW>),
                            dim3((unsigned)(t2.tiles_x * t2.tiles_y * t2.nseg)), dim3(kTX * 8), 0, s, G, C, B, cur, t2);
         return hipGetLastError();
       }
     }
-    Tiling tl = make_tiling(G, kTY, 8);
+    Tiling tl = make_tiling(G, kTY, kCheMinLz1, kCheTarget1);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,
                        tl);

@@ -445,7 +445,8 @@ def _che_velocity(w, kind, rng):
                                                 ("zalesak", (130, 20, 24), (0, 1, 0), 33)])
 def test_che_only_two_node_tiles(precision, tol, kind, shape, bc, seed):
     """The CHE-only kernel with two nodes per thread (128 x 8 tiles; forced
-    here, chosen by itself on lattices of at least 384 such blocks) against
+    here, chosen by itself on lattices of at least 5 M nodes that fill at
+    least 384 such blocks) against
     the oracle after 30 steps, and bitwise against 8-row tiles of 64: ragged
     tiles in x (70 and 65 of 128 columns, 130 = 128 + 2) and y, walls on
     every axis or on y only."""

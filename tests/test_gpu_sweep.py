@@ -163,7 +163,7 @@ def _midsize(n=8, seed=20261205):
     """Boxes of 5-30 M nodes where the library has two kernels to choose from
     and the automatic tiling rounds its segment count down to stay within its
     block target: CHE-only boxes with random sides (FP32 compute, FP32 or
-    FP16 storage; two-node 128 x 8 tiles from 384 blocks), and coupled FP32
+    FP16 storage; two-node 128 x 8 tiles from 5 M nodes and 384 blocks), and coupled FP32
     boxes whose 64 x 16 tile count divides 512 (ragged sides within those
     tiles), which take 16-row tiles."""
     rng = np.random.default_rng(seed)
