@@ -133,7 +133,8 @@ int mplb_set_stream(mplb_t* h, void* hip_stream);
 
 /* Validate and derive (beta, k, eta, tau_g) from p.  MPLB_E_INVAL if any rate
  * lies outside (0,2), s_1..s_3 differ, A is outside (0,1/3), D, rho_l,
- * rho_g or nu is not positive, or the mobility is negative. */
+ * rho_g or nu is not positive, or the mobility is negative; a refused call
+ * leaves the lattice's parameters as they were. */
 int mplb_set_params(mplb_t* h, const mplb_params* p);
 
 /* CHE-only lattices: the velocity prescribed at step n.  u_field (3N, used
@@ -148,7 +149,9 @@ int mplb_set_velocity(mplb_t* h, int kind, const double* u_field, double U, doub
  * u0) (Eq. 21), (phi u)_prev = phi0 u0, step counter 0.  phi0 has N values;
  * u0 has 3N or is NULL (u0 = 0); in CHE-only mode u0 is ignored and the
  * prescribed velocity at step 0 is used.  Requires mplb_set_params (and, in
- * CHE-only mode, mplb_set_velocity). */
+ * CHE-only mode, mplb_set_velocity).  It may be called again to restart the
+ * run; if it fails, the lattice counts as uninitialised (mplb_step returns
+ * MPLB_E_STATE) until a later mplb_init succeeds. */
 int mplb_init(mplb_t* h, const double* phi0, const double* u0);
 
 /* Advance nsteps >= 0 time steps (Eqs. 15-16 and their D3Q15 analogue; the
@@ -203,7 +206,8 @@ int mplb_front(mplb_t* h, double out[2]);
  * nsteps launches are replayed as one HIP graph, cached while the batch keeps
  * its shape.  Each lattice computes exactly what mplb_step computes for it.
  * All handles must be initialised, share one precision and mode, and use the
- * first handle's stream.  Not thread-safe across calls on one device.
+ * first handle's stream (MPLB_E_INVAL otherwise, before anything is
+ * enqueued).  Not thread-safe across calls on one device.
  * CHE-only and D3Q19 lattices, lattices with a study switch set, and a batch
  * in which some lattices have S^g = 1 off the stress moments and others not,
  * are stepped one after another (the batched kernel is the default D3Q15 step

@@ -240,7 +240,9 @@ int mplb_set_params(mplb_t* h, const mplb_params* p) {
   for (int i = 0; i < 7; ++i)
     if (!in02(p->s_f[i])) return fail(h, MPLB_E_INVAL, "s_f[%d] outside (0,2)", i);
   if (p->s_f[1] != p->s_f[2] || p->s_f[1] != p->s_f[3]) return fail(h, MPLB_E_INVAL, "s_1, s_2, s_3 must be equal");
-  Coef<double>& C = h->C;
+  // formed in a copy and committed only once every check has passed, so a
+  // refused call leaves the lattice's parameters as they were
+  Coef<double> C = h->C;
   C.rho_l = p->rho_l;
   C.rho_g = p->rho_g;
   C.drho = p->rho_l - p->rho_g;
@@ -273,6 +275,7 @@ int mplb_set_params(mplb_t* h, const mplb_params* p) {
   C.unit_rates = 1;
   for (int i = 0; i < 15; ++i)
     if ((i < 9 || i > 13) && C.lg[i] != 1.0) C.unit_rates = 0;
+  h->C = C;
   h->have_params = true;
   return MPLB_OK;
 }
@@ -324,6 +327,9 @@ static void set_vel_time(mplb_t* h) {
 int mplb_init(mplb_t* h, const double* phi0, const double* u0) {
   if (!h || !phi0) return MPLB_E_INVAL;
   if (!h->have_params) return fail(h, MPLB_E_STATE, "init before set_params");
+  // the state is overwritten from here on: a failure below leaves the
+  // lattice uninitialised rather than half of two states
+  h->have_init = false;
   size_t sT = comp_size(h->prec);
   int rc = upload_field(h, phi0, h->B.phi);
   if (rc) return rc;
@@ -549,6 +555,10 @@ static int step_many_impl(mplb_t* const* hs, int count, int nsteps, bool noalloc
     if (!hs[i]->have_init) return fail(hs[i], MPLB_E_STATE, "step before init");
     if (hs[i]->prec != hs[0]->prec || hs[i]->mode != hs[0]->mode)
       return fail(hs[0], MPLB_E_INVAL, "step_many needs one precision and one mode");
+    // the steps go to one stream, and each lattice's non-finite check reads
+    // its flag on its own stream afterwards: the two must be the same
+    if (hs[i]->stream != hs[0]->stream)
+      return fail(hs[0], MPLB_E_INVAL, "step_many needs every lattice on the first lattice's stream");
     for (int j = 0; j < i; ++j)
       if (hs[j] == hs[i]) return fail(hs[0], MPLB_E_INVAL, "a lattice appears twice in step_many");
   }
@@ -752,6 +762,7 @@ int mplb_restore(mplb_t* h, const void* host_buf, size_t bytes) {
     return fail(h, MPLB_E_INVAL, "checkpoint does not match this lattice");
   if (!h->have_params) return fail(h, MPLB_E_STATE, "restore before set_params");
   const char* p = (const char*)host_buf + sizeof hd;
+  h->have_init = false;  // as in mplb_init: a failed copy leaves no usable state
   h->cur = 0;
   HIPCHK(h, hipMemcpyAsync(h->B.f[0], p, h->plan.f, hipMemcpyHostToDevice, h->stream));
   p += h->plan.f;

@@ -524,6 +524,54 @@ def test_che_only_velocity_fixed_after_init():
     g.destroy()
 
 
+def test_refused_params_leave_the_lattice_unchanged():
+    """A set_params call that fails a check late (after densities and rates
+    have been read) changes nothing: the run continues bitwise as a run that
+    never saw the call."""
+    from paper_1507_07294_amd import mplb
+    w = wl.perturbed_case((20, 18, 16), (0, 0, 1), 52, coupled=True)
+    a, b = helpers.gpu_for(w, "f32"), helpers.gpu_for(w, "f32")
+    a.step(3)
+    b.step(3)
+    bad_rates = list(w.params.lambda_g)
+    bad_rates[14] = 2.5
+    for bad in (w.params.replace(rho_l=7.0, sigma=0.3, stencil=5),
+                w.params.replace(rho_l=7.0, nu=0.3, lambda_g=tuple(bad_rates))):
+        with pytest.raises(mplb.MplbError) as ei:
+            a.set_params(bad)
+        assert ei.value.code == mplb.MPLB_E_INVAL
+    a.step(10)
+    b.step(10)
+    fa, fb = helpers.fields_of(a), helpers.fields_of(b)
+    a.destroy()
+    b.destroy()
+    for k in fa:
+        assert np.array_equal(fa[k], fb[k]), k
+
+
+def test_step_many_refuses_lattices_on_other_streams():
+    """A batch whose lattices do not share the first lattice's stream is
+    refused before anything is enqueued (each lattice's non-finite check
+    would otherwise read its flag on a stream that the steps did not use);
+    on one stream the same batch steps."""
+    import torch
+    from paper_1507_07294_amd import mplb
+    ws = [wl.perturbed_case((16, 12, 10), (0, 0, 1), s, coupled=True) for s in (53, 54)]
+    a, b = (helpers.gpu_for(w, "f32") for w in ws)
+    other = torch.cuda.Stream()
+    b.set_stream(other.cuda_stream)
+    with pytest.raises(mplb.MplbError) as ei:
+        mplb.mplb_step_many([a, b], 2)
+    assert ei.value.code == mplb.MPLB_E_INVAL
+    assert a.step_count == 0 and b.step_count == 0
+    b.set_stream(torch.cuda.current_stream().cuda_stream)
+    mplb.mplb_step_many([a, b], 2)
+    assert a.step_count == 2 and b.step_count == 2
+    torch.cuda.synchronize()
+    a.destroy()
+    b.destroy()
+
+
 def test_totals_match_oracle():
     w = wl.perturbed_case((17, 19, 23), (0, 0, 0), 31, coupled=True, gravity=(1e-5, 0, -2e-5))
     o = helpers.oracle_for(w)
