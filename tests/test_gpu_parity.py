@@ -470,20 +470,27 @@ def test_che_only_two_node_tiles(precision, tol, kind, shape, bc, seed):
         assert e <= (tol[k] if isinstance(tol, dict) else tol), (k, e)
 
 
-def test_che_only_256_full_field():
-    """The 256^3 interface-tracking box in the launch configuration the
-    benchmark times (two nodes per thread on 128 x 8 tiles, 32-plane
-    segments, streaming stores), FP32, every node against the FP64 oracle
-    after 4 steps."""
+@functools.lru_cache(maxsize=1)
+def _che256_oracle(steps=4):
     w = wl.deformation_flow(n=256)
-    print(f"\n[case] CHE-only full field {w.shape} f32 4 steps", flush=True)
-    g = helpers.gpu_for(w, "f32")
+    o = helpers.oracle_for(w)
+    o.step(steps)
+    return w, helpers.fields_of(o, False)
+
+
+@pytest.mark.parametrize("precision,tol", [("f32", F32_TOL), ("f16", 5e-3)])
+def test_che_only_256_full_field(precision, tol):
+    """The 256^3 interface-tracking box in the launch configurations the
+    benchmark times (two nodes per thread on 128 x 8 tiles, 32-plane
+    segments, streaming stores), in FP32 and with FP16 storage of f_1..f_6,
+    every node against the FP64 oracle after 4 steps."""
+    w, ref = _che256_oracle()
+    print(f"\n[case] CHE-only full field {w.shape} {precision} 4 steps", flush=True)
+    g = helpers.gpu_for(w, precision)
     g.step(4)
     got = helpers.fields_of(g, False)
     g.destroy()
-    o = helpers.oracle_for(w)
-    o.step(4)
-    _full_field_check(w, got, helpers.fields_of(o, False), "f32", F32_TOL)
+    _full_field_check(w, got, ref, precision, tol)
 
 
 @pytest.mark.parametrize("model", ["mrt", "srt"])
