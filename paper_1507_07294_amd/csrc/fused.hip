@@ -31,6 +31,7 @@
 //
 // Finite-difference ghosts: phi beyond a wall is the mirror phi(-1) = phi(0);
 // mu at a ghost position is evaluated at its mirror image, so mu(-1) = mu(0).
+#include <atomic>
 #include <type_traits>
 
 #include "common.h"
@@ -1166,19 +1167,21 @@ constexpr size_t kNoAllocTableBytes = (size_t)MPLB_NOALLOC_MAX_LATTICES * sizeof
 static_assert(sizeof(BatchItem<double>) >= sizeof(BatchItem<float>), "the table is sized for FP64 items");
 static __device__ __align__(256) unsigned char scratch[kNoAllocTableBytes];
 constexpr int kMaxDevices = 64;
-void* g_scratch_ptr[kMaxDevices];
+// atomic: lattices may be created on several threads at once (each lookup
+// of a device stores the same address)
+std::atomic<void*> g_scratch_ptr[kMaxDevices];
 
 }  // namespace
 
 hipError_t noalloc_table(int dev, void** out) {
   if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
-  if (!g_scratch_ptr[dev]) {
-    void* p = nullptr;
+  void* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
     hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
     if (e != hipSuccess) return e;
-    g_scratch_ptr[dev] = p;
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
   }
-  *out = g_scratch_ptr[dev];
+  *out = p;
   return hipSuccess;
 }
 
