@@ -535,8 +535,20 @@ __device__ inline void fused_body(const Geo& G, const Coef<typename Prec<P>::T>&
   // warm-up: phi planes z0-2 .. z0+2 (ONEBAR) or z0+1 with the own
   // populations of z0 on, mu planes z0-1, z0 (read after the first barrier
   // of the march)
-  for (int zl = z0 - 2; zl <= z0 + (ONEBAR ? 2 : 1); ++zl)
-    ld.load(G, fin, zl, sphi[ps(zl)], zl >= z0 ? sfq[qs(zl)] : nullptr);
+  // (three planes' pulls in flight at a time: plane k is issued before
+  // plane k-2 is summed)
+  {
+    constexpr int NW = ONEBAR ? 5 : 4;
+    typename LD::Pending pw[3];
+#pragma unroll
+    for (int k = 0; k < NW + 2; ++k) {
+      if (k < NW) ld.issue(G, fin, z0 - 2 + k, pw[k % 3]);
+      if (k >= 2) {
+        const int zl = z0 - 4 + k;
+        ld.finish(pw[(k - 2) % 3], sphi[ps(zl)], zl >= z0 ? sfq[qs(zl)] : nullptr);
+      }
+    }
+  }
   __syncthreads();
   mm.template run<NPR, (V & kVarS7) != 0>(G, C, z0 - 1, sphi, smu[ms(z0 - 1)]);
   mm.template run<NPR, (V & kVarS7) != 0>(G, C, z0, sphi, smu[ms(z0)]);
@@ -718,9 +730,17 @@ k_fused_che(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
   const int lds_c = (ty + 1) * R::PX + tx + 1;
   PrescColumn<T> pc;
   pc.init(G, C, gx, gy);
-  ld.load(G, fin, z0 - 1, sphi[(z0 - 1 + 8) % 4]);
-  ld.load(G, fin, z0, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
-  ld.load(G, fin, z0 + 1, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
+  {
+    // the three planes before the march: all pulls in flight together
+    typename LD::Pending p0, p1, p2;
+    ld.issue(G, fin, z0 - 1, p0);
+    ld.issue(G, fin, z0, p1);
+    ld.issue(G, fin, z0 + 1, p2);
+    __builtin_amdgcn_sched_barrier(0);
+    ld.finish(p0, sphi[(z0 - 1 + 8) % 4], nullptr);
+    ld.finish(p1, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
+    ld.finish(p2, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
+  }
   __syncthreads();
   // plane z; PULL: also the pulls of plane z+2, which every plane but the
   // last issues (phi is read up to plane z1, the Laplacian of plane z1-1).
@@ -865,13 +885,15 @@ k_fused_che2(Geo G, Coef<typename Prec<P>::T> C, Bufs B, int cur, Tiling TL) {
     }
   };
   {
-    Pending pd;
-    issue(z0 - 1, pd);
-    finish(pd, sphi[(z0 - 1 + 8) % 4], nullptr);
-    issue(z0, pd);
-    finish(pd, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
-    issue(z0 + 1, pd);
-    finish(pd, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
+    // the three planes before the march: all pulls in flight together
+    Pending p0, p1, p2;
+    issue(z0 - 1, p0);
+    issue(z0, p1);
+    issue(z0 + 1, p2);
+    __builtin_amdgcn_sched_barrier(0);
+    finish(p0, sphi[(z0 - 1 + 8) % 4], nullptr);
+    finish(p1, sphi[(z0 + 8) % 4], sfq[z0 % 2]);
+    finish(p2, sphi[(z0 + 1 + 8) % 4], sfq[(z0 + 1) % 2]);
   }
   __syncthreads();
   auto plane = [&](int z, auto pull) {
