@@ -1024,8 +1024,26 @@ void launch_coupled(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, 
 // five planes per segment, and on the 256 x 256 x 1024 box 256-plane
 // segments took FP16 1690 -> 1618 us per step, BF16 1665 -> 1624 and FP64
 // 5300 -> 5250 (1024 blocks: 1673, 1650, 5285), same bits.  The 16-row FP32
-// step keeps two rounds (one round: 2588 -> 2674 us).
+// step keeps two rounds (one round: 2588 -> 2674 us).  FP64 runs one block
+// per CU (its registers), so its round is 256 blocks: 256 x 256 x 1024 5180
+// -> 5054 us, a W = 64 Rayleigh-Taylor box 100.5 -> 85.4 us; the FP64
+// CHE-only step likewise, 96^3 39.7 -> 35.1 us, 128^3 58.6 -> 53.6, 256^3
+// 477 -> 428 (64^3 and 192^3 within 1.5 %).
 constexpr int kTarget8 = 512;
+template <int P>
+constexpr int target8() { return P == MPLB_F64 ? 256 : kTarget8; }
+
+// A lattice stepped alone whose blocks cannot fill the chip is bound by the
+// latency of its march, not by bandwidth: segments of at least 5 planes
+// instead of 16 (more, shorter segments, each re-reading its 5 warm-up
+// planes) took a 32^3 droplet from 61.1 to 25.8 us per step in FP32 and 81.4
+// to 32.9 in FP64, 64^3 from 68.0 to 29.5, 96^3 from 71.8 to 49.1, W = 32 and
+// 48 Rayleigh-Taylor boxes from 60.5 and 67.1 to 26.1 and 31.0; boxes whose
+// segment count the block target sets (W >= 96) are unchanged (same bits).
+// The batched step keeps 16: there the lattices fill the chip together, and
+// 8 or 5 planes gave 24.5 and 24.0 GLUPS against 24.6 on the serving trace's
+// lattices in FP32, 35.0 and 31.7 against 37.5 with FP16 populations.
+constexpr int kMinLz8 = 5;
 
 // 16-row tiles only on a lattice that fills two rounds of the chip with them:
 // on small lattices (64^3: 16 blocks) they halve the blocks that run at all,
@@ -1037,7 +1055,8 @@ constexpr int kTarget8 = 512;
 constexpr int kMinBlocksTall = 512;
 
 // CHE-only tiling.  Both kernels size their segments for at most 512
-// blocks, one round of the chip at two blocks per CU.  Two nodes per thread
+// blocks, one round of the chip at two blocks per CU (FP64, one block per CU:
+// 256).  Two nodes per thread
 // (k_fused_che2, 128 x 8 tiles, segments of at least 8 planes: 32 at 256^3)
 // on lattices of at least 5 M nodes that fill at least 384 such blocks; 8-row
 // tiles of 64 (k_fused_che, segments of at least 5 planes) otherwise and for
@@ -1069,7 +1088,7 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
         return hipGetLastError();
       }
     }
-    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, 16, kTarget8), s);
+    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, kMinLz8, target8<P>()), s);
   } else {
     // the CHE-only ring re-reads only 2 planes per segment, so its segments
     // can be shorter than the coupled step's and fill the chip on small boxes
@@ -1082,7 +1101,7 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
         return hipGetLastError();
       }
     }
-    Tiling tl = make_tiling(G, kTY, kCheMinLz1, kCheTarget1);
+    Tiling tl = make_tiling(G, kTY, kCheMinLz1, P == MPLB_F64 ? target8<P>() : kCheTarget1);
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,
                        tl);
