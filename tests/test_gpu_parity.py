@@ -75,7 +75,7 @@ def test_coupled_f64(shape, bc, seed):
     ((70, 37, 29), (0, 0, 1), 12),
     ((9, 10, 11), (1, 1, 1), 13),   # walls on every axis (the x/y-wall instantiation)
     ((33, 5, 40), (0, 0, 0), 14),   # fully periodic, thin in y
-    ((67, 35, 21), (1, 1, 0), 15),  # walls on x and y; ragged x and y tails, two z segments
+    ((67, 35, 21), (1, 1, 0), 15),  # walls on x and y; ragged x and y tails, several z segments
 ])
 def test_coupled_f32(shape, bc, seed):
     """FP32 against the oracle on the geometries of the FP64 test, less the
@@ -816,8 +816,11 @@ def _sampled_check(w, precision, tol):
     got = {k: g.read(k) for k in fields}
     g.destroy()
     rng = np.random.default_rng(7)
+    # z-segment edges: 128-plane segments (16-row FP32 tiles), 256-plane
+    # (8-row 16-bit tiles) and 512-plane (FP64, one block per CU)
     nodes = [(0, 0, 0), (63, 7, 1), (64, 8, 63), (255, 255, nz - 1), (127, 128, 64), (191, 200, nz // 2),
-             (5, 250, nz // 2 + 1), (250, 3, nz - 2), (64, 7, 128), (63, 8, 127)]
+             (5, 250, nz // 2 + 1), (250, 3, nz - 2), (64, 7, 128), (63, 8, 127), (100, 100, 255), (101, 99, 256),
+             (30, 60, nz // 2 - 1), (31, 61, 767), (200, 190, 768)]
     nodes += [tuple(int(v) for v in rng.integers(0, (nx, ny, nz))) for _ in range(10)]
     ref = {k: [] for k in fields}
     val = {k: [] for k in fields}
