@@ -1040,6 +1040,12 @@ constexpr int target8() { return P == MPLB_F64 ? 256 : kTarget8; }
 // to 32.9 in FP64, 64^3 from 68.0 to 29.5, 96^3 from 71.8 to 49.1, W = 32 and
 // 48 Rayleigh-Taylor boxes from 60.5 and 67.1 to 26.1 and 31.0; boxes whose
 // segment count the block target sets (W >= 96) are unchanged (same bits).
+// A lattice between 256 and 512 blocks leaves some CUs with one block and
+// others with two; where one block per CU marches fewer plane-times (below)
+// it is taken: 72^3 droplet 42.7 -> 34.5 us in FP32 and 42.3 -> 31.6 with
+// FP16 populations, 80^3 43.8 -> 38.5, W = 56 and 64 Rayleigh-Taylor boxes
+// 44.8 -> 40.0 and 49.8 -> 47.4 (FP16 at W = 64: 38.6 -> 39.3), boxes of
+// 96^3 and 112^3, which keep two blocks per CU, unchanged.
 // The batched step keeps 16: there the lattices fill the chip together, and
 // 8 or 5 planes gave 24.5 and 24.0 GLUPS against 24.6 on the serving trace's
 // lattices in FP32, 35.0 and 31.7 against 37.5 with FP16 populations.
@@ -1088,7 +1094,19 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
         return hipGetLastError();
       }
     }
-    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, make_tiling(G, kTY, kMinLz8, target8<P>()), s);
+    Tiling t8 = make_tiling(G, kTY, kMinLz8, target8<P>());
+    if constexpr (P != MPLB_F64) {
+      // between one and two blocks per CU, the CUs that run two take about
+      // 1.3 times as long and set the step time: take one block per CU
+      // (longer segments) where its march, in planes plus about 8 planes of
+      // warm-up and start, is shorter than 1.3 times the other's
+      const int nb = t8.tiles_x * t8.tiles_y * t8.nseg;
+      if (nb > kTarget8 / 2 && nb < kTarget8) {
+        const Tiling t1 = make_tiling(G, kTY, kMinLz8, kTarget8 / 2);
+        if (10 * (t1.lz + 8) <= 13 * (t8.lz + 8)) t8 = t1;
+      }
+    }
+    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, t8, s);
   } else {
     // the CHE-only ring re-reads only 2 planes per segment, so its segments
     // can be shorter than the coupled step's and fill the chip on small boxes
