@@ -1120,6 +1120,17 @@ hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& 
       }
     }
     Tiling tl = make_tiling(G, kTY, kCheMinLz1, P == MPLB_F64 ? target8<P>() : kCheTarget1);
+    if constexpr (P != MPLB_F64) {
+      // one block per CU where the two-block tiling would leave some CUs with
+      // one and some with two, as for the coupled step (72^3 23.3 -> 18.5 us
+      // per step, 80^3 23.2 -> 20.2, 88^3 23.3 -> 21.9; FP16 storage alike;
+      // 96^3 - 128^3 unchanged)
+      const int nb = tl.tiles_x * tl.tiles_y * tl.nseg;
+      if (nb > kCheTarget1 / 2 && nb < kCheTarget1) {
+        const Tiling t1 = make_tiling(G, kTY, kCheMinLz1, kCheTarget1 / 2);
+        if (10 * (t1.lz + 8) <= 13 * (tl.lz + 8)) tl = t1;
+      }
+    }
     dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
     hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,
                        tl);
