@@ -290,6 +290,19 @@ int mplb_poison(mplb_t* h);
  * fields are bitwise the same; mplb_step_many always uses 8 rows. */
 int mplb_force_tile_rows(mplb_t* h, int rows);
 
+/* The kernel and work split that mplb_step uses for a lattice of nx*ny*nz
+ * nodes in this precision and mode, with `rows` as for mplb_force_tile_rows
+ * (0: the automatic choice).  A host computation: it needs no device and no
+ * lattice.  out[0]: 0 the coupled step on 64 x 8 tiles, 1 on 64 x 16 tiles,
+ * 2 the CHE-only step with one node per thread (64 x 8 tiles), 3 with two
+ * nodes per thread (128 x 8 tiles); out[1], out[2]: tile width and height in
+ * nodes; out[3]: planes per z segment (the last segment may be shorter);
+ * out[4]: segments; out[5]: blocks of the launch (tiles times segments).
+ * MPLB_E_INVAL for sizes, modes or precisions mplb_create refuses, or rows
+ * that mplb_force_tile_rows refuses.  Every choice gives the same results
+ * bit for bit; it sets only the speed of the step. */
+int mplb_launch_shape(int nx, int ny, int nz, int precision, int mode, int rows, int out[6]);
+
 void mplb_destroy(mplb_t* h);
 const char* mplb_last_error(const mplb_t* h);
 const char* mplb_strerror(int code);

@@ -68,6 +68,15 @@ struct Tiling {
   int tiles_x, tiles_y, lz, nseg;
 };
 
+// Kernel and work split of one step (launch_shape): the coupled step on
+// 64 x 8 or 64 x 16 tiles, the CHE-only step with one node per thread (64 x 8)
+// or two (128 x 8).
+enum ShapeKind { kShapeCoupled8 = 0, kShapeCoupled16 = 1, kShapeChe1 = 2, kShapeChe2 = 3 };
+struct Shape {
+  int kind, tile_w, tile_h;
+  Tiling tl;
+};
+
 // One lattice of a batched step: its geometry, coefficients, buffers, work
 // split, buffer parity and first block in the batch grid.
 template <class T>

@@ -1030,8 +1030,6 @@ void launch_coupled(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, 
 // CHE-only step likewise, 96^3 39.7 -> 35.1 us, 128^3 58.6 -> 53.6, 256^3
 // 477 -> 428 (64^3 and 192^3 within 1.5 %).
 constexpr int kTarget8 = 512;
-template <int P>
-constexpr int target8() { return P == MPLB_F64 ? 256 : kTarget8; }
 
 // A lattice stepped alone whose blocks cannot fill the chip is bound by the
 // latency of its march, not by bandwidth: segments of at least 5 planes
@@ -1082,58 +1080,72 @@ constexpr int kCheMinNodes2 = 5000000;
 constexpr int kCheTarget1 = 512, kCheMinLz1 = 5;
 constexpr int kCheTW = 128;
 
+}  // namespace
+
+// One block per CU instead of two-block tiling t where t would leave some CUs
+// with one block and others with two: the CUs that run two take about 1.3
+// times as long and set the step time, so the one-block split (longer
+// segments) is taken where its march, in planes plus about 8 planes of
+// warm-up and start, is shorter than 1.3 times the other's.
+static Tiling balance(const Geo& G, int TY, int min_lz, Tiling t, int target) {
+  const int nb = t.tiles_x * t.tiles_y * t.nseg;
+  if (nb > target / 2 && nb < target) {
+    const Tiling t1 = make_tiling(G, TY, min_lz, target / 2);
+    if (10 * (t1.lz + 8) <= 13 * (t.lz + 8)) return t1;
+  }
+  return t;
+}
+
+Shape launch_shape(int P, int mode, const Geo& G, int rows) {
+  if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
+    if (P == MPLB_F32) {
+      const Tiling tall = make_tiling(G, 16, 16);
+      if (rows == 16 || (rows == 0 && tall.tiles_x * tall.tiles_y * tall.nseg >= kMinBlocksTall))
+        return Shape{kShapeCoupled16, kTX, 16, tall};
+    }
+    // FP64 runs one block per CU (its registers), the other precisions two
+    Tiling t8 = make_tiling(G, kTY, kMinLz8, P == MPLB_F64 ? kTarget8 / 2 : kTarget8);
+    if (P != MPLB_F64) t8 = balance(G, kTY, kMinLz8, t8, kTarget8);
+    return Shape{kShapeCoupled8, kTX, kTY, t8};
+  }
+  if (P != MPLB_F64) {
+    const Tiling t2 = make_tiling(G, 1024 / kCheTW, kCheMinLz2, kCheTarget2, kCheTW);
+    if (rows == 16 ||
+        (rows == 0 && G.N >= kCheMinNodes2 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2))
+      return Shape{kShapeChe2, kCheTW, 1024 / kCheTW, t2};
+  }
+  Tiling tl = make_tiling(G, kTY, kCheMinLz1, P == MPLB_F64 ? kCheTarget1 / 2 : kCheTarget1);
+  if (P != MPLB_F64) tl = balance(G, kTY, kCheMinLz1, tl, kCheTarget1);
+  return Shape{kShapeChe1, kTX, kTY, tl};
+}
+
+namespace {
+
 template <int P, bool XYWALL, bool NT, int V>
 hipError_t fused_impl4(int mode, const Geo& G, const Coef<typename Prec<P>::T>& C, const Bufs& B, int cur,
                        hipStream_t s, int rows) {
+  const Shape sh = launch_shape(P, mode, G, rows);
   if (mode == MPLB_COUPLED || mode == MPLB_COUPLED_Q19) {
     constexpr int TY = coupled_ty<P>();
     if constexpr (TY != kTY) {
-      Tiling tall = make_tiling(G, TY, 16);
-      if (rows == TY || (rows == 0 && tall.tiles_x * tall.tiles_y * tall.nseg >= kMinBlocksTall)) {
-        launch_coupled<P, TY, XYWALL, NT, V>(mode, G, C, B, cur, tall, s);
+      if (sh.kind == kShapeCoupled16) {
+        launch_coupled<P, TY, XYWALL, NT, V>(mode, G, C, B, cur, sh.tl, s);
         return hipGetLastError();
       }
     }
-    Tiling t8 = make_tiling(G, kTY, kMinLz8, target8<P>());
-    if constexpr (P != MPLB_F64) {
-      // between one and two blocks per CU, the CUs that run two take about
-      // 1.3 times as long and set the step time: take one block per CU
-      // (longer segments) where its march, in planes plus about 8 planes of
-      // warm-up and start, is shorter than 1.3 times the other's
-      const int nb = t8.tiles_x * t8.tiles_y * t8.nseg;
-      if (nb > kTarget8 / 2 && nb < kTarget8) {
-        const Tiling t1 = make_tiling(G, kTY, kMinLz8, kTarget8 / 2);
-        if (10 * (t1.lz + 8) <= 13 * (t8.lz + 8)) t8 = t1;
-      }
-    }
-    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, t8, s);
+    launch_coupled<P, kTY, XYWALL, NT, V>(mode, G, C, B, cur, sh.tl, s);
   } else {
-    // the CHE-only ring re-reads only 2 planes per segment, so its segments
-    // can be shorter than the coupled step's and fill the chip on small boxes
     if constexpr (sizeof(typename Prec<P>::T) == 4) {
-      Tiling t2 = make_tiling(G, 1024 / kCheTW, kCheMinLz2, kCheTarget2, kCheTW);
-      if (rows == 16 ||
-          (rows == 0 && G.N >= kCheMinNodes2 && t2.tiles_x * t2.tiles_y * t2.nseg >= kCheMinBlocks2)) {
+      if (sh.kind == kShapeChe2) {
         hipLaunchKernelGGL((k_fused_che2<P, XYWALL, NT, V & kVarS7, kCheTW>),
-                           dim3((unsigned)(t2.tiles_x * t2.tiles_y * t2.nseg)), dim3(kTX * 8), 0, s, G, C, B, cur, t2);
+                           dim3((unsigned)(sh.tl.tiles_x * sh.tl.tiles_y * sh.tl.nseg)), dim3(kTX * 8), 0, s, G, C, B,
+                           cur, sh.tl);
         return hipGetLastError();
       }
     }
-    Tiling tl = make_tiling(G, kTY, kCheMinLz1, P == MPLB_F64 ? target8<P>() : kCheTarget1);
-    if constexpr (P != MPLB_F64) {
-      // one block per CU where the two-block tiling would leave some CUs with
-      // one and some with two, as for the coupled step (72^3 23.3 -> 18.5 us
-      // per step, 80^3 23.2 -> 20.2, 88^3 23.3 -> 21.9; FP16 storage alike;
-      // 96^3 - 128^3 unchanged)
-      const int nb = tl.tiles_x * tl.tiles_y * tl.nseg;
-      if (nb > kCheTarget1 / 2 && nb < kCheTarget1) {
-        const Tiling t1 = make_tiling(G, kTY, kCheMinLz1, kCheTarget1 / 2);
-        if (10 * (t1.lz + 8) <= 13 * (tl.lz + 8)) tl = t1;
-      }
-    }
-    dim3 grid((unsigned)(tl.tiles_x * tl.tiles_y * tl.nseg));
+    dim3 grid((unsigned)(sh.tl.tiles_x * sh.tl.tiles_y * sh.tl.nseg));
     hipLaunchKernelGGL((k_fused_che<P, kTY, XYWALL, NT, V & kVarS7>), grid, dim3(kTX * kTY), 0, s, G, C, B, cur,
-                       tl);
+                       sh.tl);
   }
   return hipGetLastError();
 }

@@ -16,6 +16,9 @@ hipError_t launch_mu(int P, const Geo& G, const Coef<double>& C, const Bufs& B, 
 // automatic choice, 8 or 16 to force one (16: FP32 populations only)
 hipError_t launch_fused_step(int P, int mode, const Geo& G, const Coef<double>& C, const Bufs& B, int cur,
                              hipStream_t s, int rows = 0);
+// the kernel and work split launch_fused_step uses (host computation only;
+// rows as there, assumed valid for P and mode)
+Shape launch_shape(int P, int mode, const Geo& G, int rows);
 // Batched coupled step over a device table of BatchItem<T> (T of P):
 // fused_batch_item_bytes gives the item size, fused_batch_fill writes item i
 // of a host table and returns that lattice's block count, launch_fused_many

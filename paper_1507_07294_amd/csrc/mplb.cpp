@@ -781,6 +781,23 @@ int mplb_copy_probe(const void* src, void* dst, size_t bytes, int kind, void* hi
   return launch_copy_probe(src, dst, bytes, kind, (hipStream_t)hip_stream) == hipSuccess ? MPLB_OK : MPLB_E_DEVICE;
 }
 
+int mplb_launch_shape(int nx, int ny, int nz, int precision, int mode, int rows, int out[6]) {
+  if (!out || !valid_dims(nx, ny, nz) || !valid_mode(mode, precision)) return MPLB_E_INVAL;
+  if (rows != 0 && rows != 8 && rows != 16) return MPLB_E_INVAL;
+  if (rows == 16 && (mode == MPLB_CHE_ONLY ? precision == MPLB_F64 : precision != MPLB_F32)) return MPLB_E_INVAL;
+  Geo G{};
+  G.nx = nx; G.ny = ny; G.nz = nz;
+  G.N = nx * ny * nz;
+  const Shape sh = launch_shape(precision, mode, G, rows);
+  out[0] = sh.kind;
+  out[1] = sh.tile_w;
+  out[2] = sh.tile_h;
+  out[3] = sh.tl.lz;
+  out[4] = sh.tl.nseg;
+  out[5] = sh.tl.tiles_x * sh.tl.tiles_y * sh.tl.nseg;
+  return MPLB_OK;
+}
+
 int mplb_force_tile_rows(mplb_t* h, int rows) {
   if (!h) return MPLB_E_INVAL;
   if (rows != 0 && rows != 8 && rows != 16) return fail(h, MPLB_E_INVAL, "tile rows must be 0, 8 or 16");

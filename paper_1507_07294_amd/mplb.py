@@ -87,6 +87,7 @@ def lib():
             "mplb_restore": (C.c_int, [vp, vp, sz]),
             "mplb_poke": (C.c_int, [vp, C.c_int, C.c_int, C.c_long, C.c_double]),
             "mplb_force_tile_rows": (C.c_int, [vp, C.c_int]),
+            "mplb_launch_shape": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, ip]),
             "mplb_poison": (C.c_int, [vp]),
             "mplb_time_stages": (C.c_int, [vp, C.c_int, dp]),
             "mplb_copy_probe": (C.c_int, [vp, vp, sz, C.c_int, vp]),
@@ -141,6 +142,21 @@ def to_params(p) -> mplb_params:
     o.forcing = int(getattr(p, "forcing", 0))
     o.lambda_override = int(getattr(p, "lambda_override", 0))
     return o
+
+
+SHAPE_KINDS = ("coupled, 64 x 8 tiles", "coupled, 64 x 16 tiles", "CHE-only, one node per thread",
+               "CHE-only, two nodes per thread")
+
+
+def mplb_launch_shape(nx, ny, nz, precision, mode, rows=0):
+    """The kernel and work split mplb_step uses for such a lattice (host
+    computation): kind (index into SHAPE_KINDS), tile width and height,
+    planes per segment, segments and blocks."""
+    out = (C.c_int * 6)()
+    rc = lib().mplb_launch_shape(nx, ny, nz, precision, mode, rows, out)
+    if rc:
+        raise MplbError(rc, "mplb_launch_shape")
+    return {"kind": out[0], "tile": (out[1], out[2]), "lz": out[3], "segments": out[4], "blocks": out[5]}
 
 
 def mplb_required_bytes(nx, ny, nz, precision, mode):

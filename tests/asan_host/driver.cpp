@@ -62,6 +62,10 @@ int main() {
   EXPECT(mplb_step(nullptr, 1) == MPLB_E_INVAL && mplb_read(nullptr, 0, nullptr) == MPLB_E_INVAL);
   EXPECT(mplb_step_many(nullptr, 1, 1) == MPLB_E_INVAL);
   mplb_destroy(nullptr);
+  int shp[6];
+  EXPECT(mplb_launch_shape(256, 256, 1024, MPLB_F32, MPLB_COUPLED, 0, shp) == MPLB_OK && shp[0] == 1 && shp[5] == 512);
+  EXPECT(mplb_launch_shape(64, 64, 64, MPLB_F64, MPLB_COUPLED, 16, shp) == MPLB_E_INVAL);
+  EXPECT(mplb_launch_shape(64, 64, 64, MPLB_F32, MPLB_CHE_ONLY, 0, nullptr) == MPLB_E_INVAL);
 
   for (int mode : {MPLB_COUPLED, MPLB_COUPLED_Q19, MPLB_CHE_ONLY})
     for (int prec : {MPLB_F64, MPLB_F32, MPLB_F32_F16, MPLB_F32_BF16}) {
