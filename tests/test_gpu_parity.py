@@ -556,6 +556,37 @@ def test_refused_params_leave_the_lattice_unchanged():
         assert np.array_equal(fa[k], fb[k]), k
 
 
+def _two_block_count(dims, min_lz):
+    """Blocks of the two-blocks-per-CU split (64 x 8 tiles, at most 512
+    blocks, segments of at least min_lz planes), computed here on its own."""
+    nx, ny, nz = dims
+    cols = -(-nx // 64) * -(-ny // 8)
+    want = max(1, 512 // cols)
+    lz = min(max(-(-nz // want), min_lz), nz)
+    return cols * -(-nz // lz)
+
+
+@pytest.mark.parametrize("dims,bc,prec,coupled", [((70, 77, 69), (0, 0, 1), "f32", True),
+                                                 ((72, 72, 72), (1, 1, 1), "f16", True),
+                                                 ((70, 75, 80), (0, 1, 0), "f32", False),
+                                                 ((80, 80, 80), (0, 0, 0), "f16", False)])
+def test_one_block_per_cu_split_matches_oracle(dims, bc, prec, coupled):
+    """Lattices that the two-block split would leave with some CUs running
+    one block and others two run one block per CU (longer segments): the
+    launch shape says so, and the fields after 6 steps match the oracle at
+    the tolerance of the precision (ragged boxes, walls on z, on every axis
+    or on y)."""
+    from paper_1507_07294_amd import mplb
+    mode = mplb.MPLB_COUPLED if coupled else mplb.MPLB_CHE_ONLY
+    sh = mplb.mplb_launch_shape(*dims, mplb.PRECISIONS[prec], mode)
+    assert sh["blocks"] <= 256 < _two_block_count(dims, 5), sh
+    w = wl.perturbed_case(dims, bc, 77 + dims[0], coupled=coupled)
+    if not coupled:
+        w.velocity = {"kind": "deformation", "U": 0.02, "T": 0.05}
+    tol = F32_TOL if prec == "f32" else 5e-3
+    _compare(w, [1, 6], prec, tol, coupled=coupled)
+
+
 def test_step_many_refuses_lattices_on_other_streams():
     """A batch whose lattices do not share the first lattice's stream is
     refused before anything is enqueued (each lattice's non-finite check
